@@ -1,0 +1,163 @@
+/*
+ * clgc.h -- C ABI of the MI355X (gfx950) library for complex Langevin (CL)
+ * dynamics of SU(3) lattice gauge theory with a theta term and adaptive
+ * SL(3,C) gauge cooling (Bongiovanni, Aarts, Seiler, Sexty, Stamatescu,
+ * "Adaptive gauge cooling for complex Langevin dynamics", LATTICE 2013).
+ *
+ * The library holds no torch types: callers pass plain device pointers (a
+ * buffer they own, e.g. a torch tensor's data_ptr) and a hipStream_t as
+ * void*.  Every entry point returns a cl_status; on failure the thread-local
+ * message from cl_last_error() says why.  Calls on one lattice are
+ * stream-ordered and must come from one thread at a time; distinct lattices
+ * are independent.
+ *
+ * Conventions (shared with the host link layout used by set/get_links):
+ *   sites   s = x0 + L0*(x1 + L1*(x2 + L2*x3)), x0 fastest; periodic;
+ *   links   host array of V*4*18 doubles: [s][mu][row][col][re,im];
+ *   inverse U^{-1} = adj(U) (links stay in SL(3,C): det U = 1);
+ *   basis   Gell-Mann lambda_a, Tr(lambda_a lambda_b) = 2 delta_ab;
+ *   noise   Philox4x32-10, counter (4*s+mu, CL step n, draw j, stream tag),
+ *           key = seed; eta_a with <eta_a eta_b> = 2 delta_ab;
+ *   extents even and >= 2 (the cooling sweep is checkerboarded).
+ */
+#ifndef CLGC_H
+#define CLGC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cl_lattice cl_lattice;
+
+typedef enum {
+    CL_OK = 0,
+    CL_EINVAL = -1,      /* bad argument: odd/too small extent, NULL pointer, size mismatch */
+    CL_ENOMEM = -2,      /* caller's device buffer too small */
+    CL_EHIP = -3,        /* a HIP runtime call failed */
+    CL_ENONFINITE = -4,  /* drift or unitarity norm became non-finite: the run is not advanced */
+    CL_EBUDGET = -5      /* a served run can never fit the server's HBM budget */
+} cl_status;
+
+typedef enum { CL_FP64 = 0, CL_MIXED = 1 } cl_precision;
+
+/* Adaptive cooling strength alpha_ad = alpha / D (section on adaptive gauge
+ * cooling): D_0 = 1, D_1 = Tr U U^dagger averaged over links (UN / 4V),
+ * D_2 = mean over (a, x) of |f_ax|, each on the configuration entering the
+ * cooling step. */
+typedef enum { CL_ALPHA_FIXED = 0, CL_ALPHA_UNORM = 1, CL_ALPHA_GRAD = 2 } cl_alpha_mode;
+
+typedef struct {
+    int32_t dims[4];     /* L0..L3, each even and >= 2 */
+    double beta;         /* Wilson coupling, > 0 */
+    double theta_re;     /* theta_L (complex: real theta -> complex action, */
+    double theta_im;     /*   imaginary theta -> real action) */
+    int32_t precision;   /* cl_precision */
+    uint64_t seed;       /* Philox key */
+} cl_lattice_desc;
+
+typedef struct {
+    double eps0;         /* nominal Langevin step */
+    int32_t adaptive;    /* 0: eps = eps0; 1: eps_n = min(eps0, B / Kmax_n) */
+    double drift_bound;  /* B; <= 0: B = eps0 * Kmax of the first adaptive step */
+} cl_step_desc;
+
+typedef struct {
+    int32_t n_steps;     /* cooling steps (each an even then an odd half-sweep), 0..64 */
+    double eps_c;        /* epsilon of Omega_x = exp(-eps alpha_ad f_ax lambda_a) */
+    double alpha;        /* alpha_gf */
+    int32_t mode;        /* cl_alpha_mode */
+} cl_cool_desc;
+
+typedef struct {
+    double plaq[2];      /* (1/18V) sum_x sum_{mu<nu} Tr U_{mu nu}(x), complex */
+    double q[2];         /* Q_L = sum_x q_L(x), clover form, complex */
+    double action[2];    /* S = S_W - i theta Q_L, complex */
+    double unorm_d;      /* d = (1/12V) sum Tr(U U^dagger - 1) of the current links */
+    double d_pre;        /* d right after the last CL update, before cooling */
+    double eps;          /* step size of the last CL update */
+    double kmax;         /* max over links of ||Khat|| of the last CL update */
+    double alpha;        /* alpha_ad of the last cooling step */
+    double bound;        /* adaptive step-size bound B (<= 0: not set yet) */
+    int64_t step;        /* CL steps taken (the next update uses Philox step = this) */
+} cl_obs;
+
+/* Bytes of device memory a lattice needs (links, clover field, drift,
+ * reduction scratch, control block).  desc as for cl_lattice_create. */
+cl_status cl_lattice_bytes(const cl_lattice_desc* desc, size_t* device_bytes);
+
+/* Create a lattice inside dev_buf (device memory of at least
+ * cl_lattice_bytes, 256-byte aligned, owned by the caller and kept alive
+ * until cl_lattice_destroy).  hip_stream: the hipStream_t every call on this
+ * lattice is ordered on (NULL = the default stream).  The links start cold
+ * (U = 1). */
+cl_status cl_lattice_create(const cl_lattice_desc* desc, void* dev_buf, size_t buf_bytes,
+                            void* hip_stream, cl_lattice** out);
+cl_status cl_lattice_destroy(cl_lattice* lat);
+
+/* perturbed = 0: cold start U = 1.  perturbed = 1: U = exp(i lambda_a (x_a + i y_a))
+ * with x_a ~ N(0, sigma_x^2), y_a ~ N(0, sigma_y^2) from Philox stream tag 1
+ * (draws 0..3 give x_1..x_8, draws 4..7 give y_1..y_8).  Resets the step counter
+ * and the adaptive bound.  Asynchronous. */
+cl_status cl_lattice_init(cl_lattice* lat, int perturbed, double sigma_x, double sigma_y);
+
+/* Copy all links from / to a host array of V*4*18 doubles (layout above).
+ * Synchronous on the lattice's stream. */
+cl_status cl_lattice_set_links(cl_lattice* lat, const double* host, size_t n_doubles);
+cl_status cl_lattice_get_links(cl_lattice* lat, double* host, size_t n_doubles);
+
+/* Step counter n and adaptive bound B (for checkpoint / resume).  Synchronous. */
+cl_status cl_lattice_get_state(cl_lattice* lat, int64_t* step, double* bound);
+cl_status cl_lattice_set_state(cl_lattice* lat, int64_t step, double bound);
+
+/* One CL update of every link (section on SU(3) with a theta term; the
+ * update itself is the standard CL step the paper alternates with cooling):
+ *   Khat = -sum_a lambda_a D_a S,  S = S_W - i theta Q_L,
+ *   U <- exp(i (eps_n Khat + sqrt(eps_n) eta_a lambda_a)) U,  U <- U det(U)^{-1/3}.
+ * All links move from the same configuration.  eps_used: if non-NULL the
+ * call waits for the stream and returns eps_n; if NULL it is asynchronous.
+ * Returns CL_ENONFINITE (and leaves the links unchanged) if the drift is not
+ * finite -- detected at the next synchronising call when asynchronous. */
+cl_status cl_langevin_step(cl_lattice* lat, const cl_step_desc* step, double* eps_used);
+
+/* n_steps adaptive gauge-cooling steps (section on gauge cooling, eq. for
+ * Omega_x and f_ax): at every site x of one parity, then the other,
+ *   f_ax = 2 Tr[lambda_a sum_mu (U_{x,mu} U_{x,mu}^dagger - U_{x-mu,mu}^dagger U_{x-mu,mu})],
+ *   Omega_x = exp(-eps_c alpha_ad f_ax lambda_a),
+ *   U_{x,mu} <- Omega_x U_{x,mu},  U_{x-mu,mu} <- U_{x-mu,mu} Omega_x^{-1}.
+ * unorm_after: if non-NULL, waits and returns d of the cooled links. */
+cl_status cl_gauge_cool(cl_lattice* lat, const cl_cool_desc* cool, double* unorm_after);
+
+/* d = (1/12V) sum_{x,mu} Tr(U U^dagger - 1) of the current links (the
+ * distance from SU(3) averaged over links).  Synchronous. */
+cl_status cl_unitarity_norm(cl_lattice* lat, double* d);
+
+/* Plaquette, topological charge (clover form of the signed-index density),
+ * action, distance and the control state.  Synchronous. */
+cl_status cl_measure(cl_lattice* lat, cl_obs* out);
+
+/* Drift Khat of every link for the current configuration, copied to a host
+ * array in the link layout (V*4*18 doubles).  Synchronous; for inspection
+ * and tests, not needed by a simulation. */
+cl_status cl_compute_drift(cl_lattice* lat, double* host_K, size_t n_doubles);
+
+/* Per-cooling-step history of the last cl_gauge_cool / cl_run_steps call:
+ * unorm[i] = sum Tr U U^dagger entering cooling step i (i = 0..n), alpha[i] =
+ * alpha_ad used by step i.  cap: room in each array.  Synchronous. */
+cl_status cl_cool_history(cl_lattice* lat, double* unorm, double* alpha, int cap, int* n);
+
+/* n_steps x (one CL update + cooling), all enqueued without host
+ * synchronisation (what a production loop runs).  Asynchronous. */
+cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_desc* cool,
+                       int n_steps);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* cl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLGC_H */

@@ -1,0 +1,222 @@
+"""Complex Langevin + adaptive gauge cooling for SU(3) with a theta term on
+MI355X (gfx950).
+
+Thin ctypes binding of the C ABI in include/clgc.h: argument marshalling
+only.  Every step of the method runs in the HIP kernels of libclgc.so;
+PyTorch only provides device memory and the stream.  If the library is not
+built this module raises on import -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+# torch first: the library then binds to the HIP runtime torch already loaded
+# (both export the soname libamdhip64.so.7), so the process has one runtime
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclgc.so")
+
+CL_OK, CL_EINVAL, CL_ENOMEM, CL_EHIP, CL_ENONFINITE, CL_EBUDGET = 0, -1, -2, -3, -4, -5
+CL_FP64, CL_MIXED = 0, 1
+CL_ALPHA_FIXED, CL_ALPHA_UNORM, CL_ALPHA_GRAD = 0, 1, 2
+
+
+class cl_lattice_desc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("beta", ctypes.c_double), ("theta_re", ctypes.c_double),
+                ("theta_im", ctypes.c_double), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class cl_step_desc(ctypes.Structure):
+    _fields_ = [("eps0", ctypes.c_double), ("adaptive", ctypes.c_int32), ("drift_bound", ctypes.c_double)]
+
+
+class cl_cool_desc(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("eps_c", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("mode", ctypes.c_int32)]
+
+
+class cl_obs(ctypes.Structure):
+    _fields_ = [("plaq", ctypes.c_double * 2), ("q", ctypes.c_double * 2), ("action", ctypes.c_double * 2),
+                ("unorm_d", ctypes.c_double), ("d_pre", ctypes.c_double), ("eps", ctypes.c_double),
+                ("kmax", ctypes.c_double), ("alpha", ctypes.c_double), ("bound", ctypes.c_double),
+                ("step", ctypes.c_int64)]
+
+
+class ClError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"clgc error {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                          "(the HIP library is the only implementation; there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, dp, sz = ctypes.c_void_p, P(ctypes.c_double), ctypes.c_size_t
+    sigs = {
+        "cl_lattice_bytes": [P(cl_lattice_desc), P(sz)],
+        "cl_lattice_create": [P(cl_lattice_desc), vp, sz, vp, P(vp)],
+        "cl_lattice_destroy": [vp],
+        "cl_lattice_init": [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double],
+        "cl_lattice_set_links": [vp, dp, sz],
+        "cl_lattice_get_links": [vp, dp, sz],
+        "cl_lattice_get_state": [vp, P(ctypes.c_int64), dp],
+        "cl_lattice_set_state": [vp, ctypes.c_int64, ctypes.c_double],
+        "cl_langevin_step": [vp, P(cl_step_desc), dp],
+        "cl_gauge_cool": [vp, P(cl_cool_desc), dp],
+        "cl_unitarity_norm": [vp, dp],
+        "cl_measure": [vp, P(cl_obs)],
+        "cl_compute_drift": [vp, dp, sz],
+        "cl_cool_history": [vp, dp, dp, ctypes.c_int, P(ctypes.c_int)],
+        "cl_run_steps": [vp, P(cl_step_desc), P(cl_cool_desc), ctypes.c_int],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.cl_last_error.argtypes = []
+    lib.cl_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != CL_OK:
+        raise ClError(status, lib.cl_last_error().decode())
+    return status
+
+
+def _dp(a):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_desc(dims, beta, theta=0.0, precision=CL_FP64, seed=0):
+    th = complex(theta)
+    return cl_lattice_desc((ctypes.c_int32 * 4)(*dims), float(beta), th.real, th.imag, int(precision), int(seed))
+
+
+def cl_lattice_bytes(desc):
+    n = ctypes.c_size_t()
+    _check(lib.cl_lattice_bytes(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+class Lattice:
+    """One CL run: links, clover field, drift and control state in a torch
+    device buffer, all work on one HIP stream."""
+
+    def __init__(self, dims, beta, theta=0.0, precision=CL_FP64, seed=0, device="cuda:0", stream=None):
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.beta = float(beta)
+        self.theta = complex(theta)
+        self.precision = precision
+        self.desc = make_desc(self.dims, beta, theta, precision, seed)
+        nbytes = cl_lattice_bytes(self.desc)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the caching allocator returns 512-byte aligned blocks; keep 256 of slack anyway
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self.buf.data_ptr()
+        aligned = (ptr + 255) & ~255
+        self.nbytes = nbytes
+        h = ctypes.c_void_p()
+        _check(lib.cl_lattice_create(ctypes.byref(self.desc), ctypes.c_void_p(aligned), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    # -- lifecycle -------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib.cl_lattice_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- state -----------------------------------------------------------
+    def init(self, perturbed=True, sigma_x=0.3, sigma_y=0.05):
+        _check(lib.cl_lattice_init(self.handle, int(perturbed), float(sigma_x), float(sigma_y)))
+
+    def set_links(self, links):
+        a = np.ascontiguousarray(np.asarray(links, dtype=np.float64).reshape(-1))
+        _check(lib.cl_lattice_set_links(self.handle, _dp(a), a.size))
+
+    def get_links(self):
+        a = np.zeros(self.V * 72)
+        _check(lib.cl_lattice_get_links(self.handle, _dp(a), a.size))
+        return a.reshape(self.V, 4, 18)
+
+    def get_state(self):
+        n, b = ctypes.c_int64(), ctypes.c_double()
+        _check(lib.cl_lattice_get_state(self.handle, ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    def set_state(self, step, bound):
+        _check(lib.cl_lattice_set_state(self.handle, int(step), float(bound)))
+
+    # -- method ----------------------------------------------------------
+    def langevin_step(self, eps0, adaptive=False, drift_bound=0.0, sync=True):
+        sd = cl_step_desc(float(eps0), int(adaptive), float(drift_bound))
+        if sync:
+            e = ctypes.c_double()
+            _check(lib.cl_langevin_step(self.handle, ctypes.byref(sd), ctypes.byref(e)))
+            return e.value
+        _check(lib.cl_langevin_step(self.handle, ctypes.byref(sd), None))
+        return None
+
+    def gauge_cool(self, n_steps, eps_c, alpha=1.0, mode=CL_ALPHA_FIXED, sync=True):
+        cd = cl_cool_desc(int(n_steps), float(eps_c), float(alpha), int(mode))
+        if sync:
+            d = ctypes.c_double()
+            _check(lib.cl_gauge_cool(self.handle, ctypes.byref(cd), ctypes.byref(d)))
+            return d.value
+        _check(lib.cl_gauge_cool(self.handle, ctypes.byref(cd), None))
+        return None
+
+    def run_steps(self, n, eps0, adaptive, n_cool, eps_c, alpha=1.0, mode=CL_ALPHA_FIXED, drift_bound=0.0):
+        sd = cl_step_desc(float(eps0), int(adaptive), float(drift_bound))
+        cd = cl_cool_desc(int(n_cool), float(eps_c), float(alpha), int(mode))
+        _check(lib.cl_run_steps(self.handle, ctypes.byref(sd), ctypes.byref(cd), int(n)))
+
+    def unitarity_norm(self):
+        d = ctypes.c_double()
+        _check(lib.cl_unitarity_norm(self.handle, ctypes.byref(d)))
+        return d.value
+
+    def measure(self):
+        o = cl_obs()
+        _check(lib.cl_measure(self.handle, ctypes.byref(o)))
+        return {"plaq": complex(o.plaq[0], o.plaq[1]), "q": complex(o.q[0], o.q[1]),
+                "action": complex(o.action[0], o.action[1]), "d": o.unorm_d, "d_pre": o.d_pre,
+                "eps": o.eps, "kmax": o.kmax, "alpha": o.alpha, "bound": o.bound, "step": o.step}
+
+    def compute_drift(self):
+        a = np.zeros(self.V * 72)
+        _check(lib.cl_compute_drift(self.handle, _dp(a), a.size))
+        return a.reshape(self.V, 4, 18)
+
+    def cool_history(self):
+        un = np.zeros(65)
+        al = np.zeros(64)
+        n = ctypes.c_int()
+        _check(lib.cl_cool_history(self.handle, _dp(un), _dp(al), 65, ctypes.byref(n)))
+        return un[:n.value + 1], al[:n.value]

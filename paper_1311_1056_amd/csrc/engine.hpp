@@ -1,0 +1,44 @@
+// engine.hpp -- internal interface between the C ABI (api.cpp) and the
+// kernels (kernels.hip).  Not installed; the public interface is clgc.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+#include "philox.hpp"
+#include "su3.hpp"
+
+namespace clgc {
+
+// one launch of a batch: device header and run table, logical blocks per kind
+struct Launch {
+    const BatchHdr* hdr;
+    const RunArgs* runs;
+    int blocks[NKIND];
+    hipStream_t stream;
+};
+
+hipError_t launch_init(const Launch& L, int prec, int perturbed, double sx, double sy);
+hipError_t launch_unorm(const Launch& L, int prec);
+hipError_t launch_unpack(const Launch& L, int prec, const double* aos);
+hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos);
+hipError_t launch_clover(const Launch& L, int prec);
+hipError_t launch_drift(const Launch& L, int prec, bool theta);
+hipError_t launch_update(const Launch& L, int prec);
+hipError_t launch_cool(const Launch& L, int prec, int parity, int iter);
+hipError_t launch_gradnorm(const Launch& L, int prec, int iter);
+hipError_t launch_measure(const Launch& L, int prec);
+hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st);
+hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st);
+
+// logical blocks a run of V sites needs per kind
+inline void blocks_per_kind(int V, int out[NKIND])
+{
+    out[KIND_LINK] = (4 * V + kBlock - 1) / kBlock;
+    out[KIND_SITE] = (V + kBlock - 1) / kBlock;
+    out[KIND_COOL] = (2 * V + kBlock - 1) / kBlock;
+    out[KIND_PLANE] = (6 * V + kBlock - 1) / kBlock;
+}
+
+constexpr int kNumPartials = 7;  // the most partial values any kernel publishes
+
+}  // namespace clgc

@@ -1,0 +1,870 @@
+// kernels.hip -- gfx950 kernels of the complex Langevin + adaptive gauge
+// cooling hot path.  No MFMA: the work is 3x3 complex products, which do not
+// map onto dense matrix-core tiles; everything is FP64 (or FP32) VALU code
+// with coalesced complex-element SoA loads (see lattice.hpp).
+//
+// Every kernel walks logical blocks of a batch of runs (a single lattice is a
+// batch of one) and reduces per-run scalars deterministically: each logical
+// block writes its partial, the last block of the run to arrive (atomic
+// counter) sums the partials in a fixed order and updates the run's control
+// block, so no host round trip sits between the kernels of a step.
+#include "engine.hpp"
+
+#include <math.h>
+
+namespace clgc {
+
+// ---------------------------------------------------------------------------
+// reductions
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum (or max) of NV values over the block; the result is valid in thread 0.
+// The order of operations is fixed, so the result depends on the inputs only.
+template <int NV, bool MAX = false>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double* lds /* NV*4 */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const double w = MAX ? wave_max(v[j]) : wave_sum(v[j]);
+        if (lane == 0) lds[j * 4 + wave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            v[j] = MAX ? fmax(fmax(lds[j * 4], lds[j * 4 + 1]), fmax(lds[j * 4 + 2], lds[j * 4 + 3]))
+                       : (lds[j * 4] + lds[j * 4 + 1]) + (lds[j * 4 + 2] + lds[j * 4 + 3]);
+        }
+    }
+    __syncthreads();
+}
+
+// Publish this logical block's partials and report whether it is the last
+// block of its run to do so.  Thread 0 holds v[] (from block_reduce).
+template <int NV>
+__device__ __forceinline__ bool publish_partials(const RunArgs& ra, int kind, int lb, const double (&v)[NV],
+                                                 uint32_t* cnt)
+{
+    __shared__ int s_last;
+    const int nblk = ra.nblk[kind];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            __hip_atomic_store(&ra.part[j * nblk + lb], v[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const uint32_t prev = atomicAdd(cnt, 1u);
+        s_last = (prev == (uint32_t)(nblk - 1));
+        if (s_last) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const bool last = s_last != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Fixed-order sum (or max) of one partial array of the run; valid in thread 0.
+template <bool MAX = false>
+__device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, int j, double* lds)
+{
+    const int nblk = ra.nblk[kind];
+    double acc = MAX ? 0.0 : 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kBlock) {
+        const double p = __hip_atomic_load(&ra.part[j * nblk + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        acc = MAX ? (isnan(p) || isnan(acc) ? NAN : fmax(acc, p)) : acc + p;
+    }
+    double v[1] = {acc};
+    block_reduce<1, MAX>(v, lds);
+    return v[0];
+}
+
+// ---------------------------------------------------------------------------
+// logical-block iteration
+
+#define CLGC_FOR_BLOCKS(KIND)                                                  \
+    for (int gb_ = blockIdx.x; gb_ < hdr->total[KIND]; gb_ += gridDim.x) {     \
+        const int run_ = find_run(hdr, KIND, gb_);                             \
+        const RunArgs& ra = runs[run_];                                        \
+        const int lb = gb_ - hdr->begin[KIND][run_];                           \
+        const int tid = lb * kBlock + (int)threadIdx.x;
+
+#define CLGC_END_BLOCKS }
+
+// decompose a link index l in [0, 4V): l = (mu * 2 + p) * Vh + h
+__device__ __forceinline__ void link_decompose(const RunArgs& ra, int l, int& mu, int& p, int& h)
+{
+    mu = l / ra.V;
+    const int rem = l - mu * ra.V;
+    p = rem >= ra.Vh;
+    h = rem - p * ra.Vh;
+}
+
+template <typename T>
+__device__ __forceinline__ mat3<T> ldU(const RunArgs& ra, int mu, const Site& s)
+{
+    return load_mat((const cx<T>*)ra.U, link_off(ra, mu, s), 4 * ra.V);
+}
+
+// ---------------------------------------------------------------------------
+// initial configuration
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_init(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+                                                 int perturbed, double sx, double sy)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_LINK)
+    double un = 0.0;
+    if (tid < 4 * ra.V) {
+        int mu, p, h;
+        link_decompose(ra, tid, mu, p, h);
+        mat3<double> U = m_id<double>();
+        if (perturbed) {
+            const Site s = site_coords(ra, p, h);
+            const uint32_t c0 = (uint32_t)(4 * site_lex(ra, s) + mu);
+            double xr[8], yr[8];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double n0, n1;
+                normal_pair<double>(ra.seed, c0, 0u, (uint32_t)j, kStreamInit, n0, n1);
+                xr[2 * j] = sx * n0;
+                xr[2 * j + 1] = sx * n1;
+                normal_pair<double>(ra.seed, c0, 0u, (uint32_t)(j + 4), kStreamInit, n0, n1);
+                yr[2 * j] = sy * n0;
+                yr[2 * j + 1] = sy * n1;
+            }
+            // A = i sum_a (x_a + i y_a) lambda_a = sum_a (-y_a + i x_a) lambda_a
+            cx<double> c[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) c[a] = {-yr[a], xr[a]};
+            const double r3 = 0.57735026918962576451;  // 1/sqrt(3)
+            mat3<double> A;
+            A.e[0][0] = c[2] + r3 * c[7];
+            A.e[1][1] = r3 * c[7] - c[2];
+            A.e[2][2] = (-2.0 * r3) * c[7];
+            // lambda_1, lambda_2: (0,1) = c1 - i c2, (1,0) = c1 + i c2
+            A.e[0][1] = c[0] + cx<double>{c[1].im, -c[1].re};
+            A.e[1][0] = c[0] + cx<double>{-c[1].im, c[1].re};
+            A.e[0][2] = c[3] + cx<double>{c[4].im, -c[4].re};
+            A.e[2][0] = c[3] + cx<double>{-c[4].im, c[4].re};
+            A.e[1][2] = c[5] + cx<double>{c[6].im, -c[6].re};
+            A.e[2][1] = c[5] + cx<double>{-c[6].im, c[6].re};
+            U = m_exp_traceless(A);
+        }
+        const mat3<T> Ut = m_cast_from<T>(U);
+        store_mat((cx<T>*)ra.U, tid, 4 * ra.V, Ut);
+        un = (double)m_norm2(Ut);
+    }
+    double v[1] = {un};
+    block_reduce<1>(v, lds);
+    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_UPDATE])) {
+        const double tot = gather_partials(ra, KIND_LINK, 0, lds);
+        if (threadIdx.x == 0) {
+            Ctrl* c = ra.ctrl;
+            c->unorm = tot;
+            c->step = 0;
+            c->bound = 0.0;
+            c->eps = 0.0;
+            c->kmax = 0.0;
+            c->d_pre = tot / (12.0 * ra.V) - 1.0;
+            c->status = ST_OK;
+            c->hist_n = 0;
+            c->alpha_cur = 0.0;
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// unitarity norm of the current links (after links are written from the host)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_unorm(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_LINK)
+    double un = 0.0;
+    if (tid < 4 * ra.V) un = (double)m_norm2(load_mat((const cx<T>*)ra.U, tid, 4 * ra.V));
+    double v[1] = {un};
+    block_reduce<1>(v, lds);
+    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_UPDATE])) {
+        const double tot = gather_partials(ra, KIND_LINK, 0, lds);
+        if (threadIdx.x == 0) {
+            ra.ctrl->unorm = tot;
+            ra.ctrl->status = isfinite(tot) ? ra.ctrl->status : (int)ST_NONFINITE;
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// host AoS (double, lexicographic) <-> device SoA (T, checkerboard)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_unpack(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+                                                   const double* __restrict__ aos)
+{
+    CLGC_FOR_BLOCKS(KIND_LINK)
+    if (tid < 4 * ra.V) {
+        int mu, p, h;
+        link_decompose(ra, tid, mu, p, h);
+        const Site s = site_coords(ra, p, h);
+        const double* src = aos + ((size_t)site_lex(ra, s) * 4 + mu) * 18;
+        mat3<T> m;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) m.e[e / 3][e % 3] = {T(src[2 * e]), T(src[2 * e + 1])};
+        store_mat((cx<T>*)ra.U, tid, 4 * ra.V, m);
+    }
+    CLGC_END_BLOCKS
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pack(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+                                                 const void* __restrict__ field, double* __restrict__ aos)
+{
+    CLGC_FOR_BLOCKS(KIND_LINK)
+    if (tid < 4 * ra.V) {
+        int mu, p, h;
+        link_decompose(ra, tid, mu, p, h);
+        const Site s = site_coords(ra, p, h);
+        double* dst = aos + ((size_t)site_lex(ra, s) * 4 + mu) * 18;
+        const mat3<T> m = load_mat((const cx<T>*)field, tid, 4 * ra.V);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            dst[2 * e] = (double)m.e[e / 3][e % 3].re;
+            dst[2 * e + 1] = (double)m.e[e / 3][e % 3].im;
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// ---------------------------------------------------------------------------
+// clover field: F_{mu nu}(x) = sum over the four counter-clockwise leaves L at
+// x in the (mu, nu) plane of (L - L^{-1})
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+{
+    CLGC_FOR_BLOCKS(KIND_PLANE)
+    if (tid < 6 * ra.V) {
+        const int P = tid / ra.V;
+        const int rem = tid - P * ra.V;
+        const int p = rem >= ra.Vh;
+        const int h = rem - p * ra.Vh;
+        const int mu = P < 3 ? 0 : (P < 5 ? 1 : 2);
+        const int nu = P < 3 ? P + 1 : (P < 5 ? P - 1 : 3);
+        const Site x = site_coords(ra, p, h);
+        const Site xpm = site_move(ra, x, mu, +1), xpn = site_move(ra, x, nu, +1);
+        const Site xmm = site_move(ra, x, mu, -1), xmn = site_move(ra, x, nu, -1);
+        const Site xmmpn = site_move(ra, xmm, nu, +1), xmmmn = site_move(ra, xmm, nu, -1);
+        const Site xmnpm = site_move(ra, xmn, mu, +1);
+        const mat3<T> Umx = ldU<T>(ra, mu, x), Unx = ldU<T>(ra, nu, x);
+        const mat3<T> Umxmm = ldU<T>(ra, mu, xmm), Unxmn = ldU<T>(ra, nu, xmn);
+        mat3<T> F = m_zero<T>();
+        mat3<T> L;
+        // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
+        L = (Umx * ldU<T>(ra, nu, xpm)) * m_adj(Unx * ldU<T>(ra, mu, xpn));
+        F = F + (L - m_adj(L));
+        // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
+        L = Unx * (m_adj(ldU<T>(ra, nu, xmm) * ldU<T>(ra, mu, xmmpn)) * Umxmm);
+        F = F + (L - m_adj(L));
+        // [U_nu(x-mu-nu) U_mu(x-mu)]^{-1} U_mu(x-mu-nu) U_nu(x-nu)
+        L = m_adj(ldU<T>(ra, nu, xmmmn) * Umxmm) * (ldU<T>(ra, mu, xmmmn) * Unxmn);
+        F = F + (L - m_adj(L));
+        // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
+        L = m_adj(Unxmn) * ((ldU<T>(ra, mu, xmn) * ldU<T>(ra, nu, xmnpm)) * m_adj(Umx));
+        F = F + (L - m_adj(L));
+        store_mat((cx<T>*)ra.F, tid, 6 * ra.V, F);
+    }
+    CLGC_END_BLOCKS
+}
+
+// ---------------------------------------------------------------------------
+// drift
+//
+// For link (x, mu) each of the six loops through it is Gamma = e0 e1 e2 e3
+// with corners d0 = x, d1 = x+mu, d2 = x+mu+s nu, d3 = x+s nu.  With the
+// staple A = e1 e2 e3 (d1 -> d0) and its inverse A' = e3' e2' e1':
+//   Khat_W     = (i beta/3) TL( e0 sum A - sum A' e0' ),
+//   Khat_theta = theta/(128 pi^2) TL( e0 sum sigma I + sum sigma J e0' ),
+//   I = X1 e1e2e3 + e1 X2 e2e3 + e1e2 X3 e3 + e1e2e3 X0     (Horner, 8 products),
+//   J = X0 e3'e2'e1' + e3' X3 e2'e1' + e3'e2' X2 e1' + e3'e2'e1' X1   (8 products),
+// X_k the dual clover matrix of the loop's plane at d_k, sigma = s sign(nu - mu).
+// The two accumulators Lacc = cb A + ct sigma I and Racc = cb A' - ct sigma J
+// give Khat = TL(e0 Lacc - Racc e0').
+
+template <typename T, bool THETA>
+__global__ void __launch_bounds__(kBlock) k_drift(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_LINK)
+    double kn2 = 0.0;
+    if (tid < 4 * ra.V) {
+        int mu, p, h;
+        link_decompose(ra, tid, mu, p, h);
+        const Site x = site_coords(ra, p, h);
+        const Site d1 = site_move(ra, x, mu, +1);
+        const cx<T> cb = {T(0), T(ra.beta / 3.0)};
+        const double tn = 1.0 / (128.0 * M_PI * M_PI);
+        const cx<T> ct = {T(ra.th_re * tn), T(ra.th_im * tn)};
+        const cx<T>* __restrict__ Fb = (const cx<T>*)ra.F;
+        mat3<T> Lacc = m_zero<T>(), Racc = m_zero<T>();
+#pragma unroll 1
+        for (int nn = 0; nn < 3; ++nn) {
+            const int nu = nn + (nn >= mu);
+            const int P = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
+            const int Pd = dual_plane(P);
+            const int fo = Pd * ra.V;
+#pragma unroll 1
+            for (int si = 0; si < 2; ++si) {
+                const int s = si ? -1 : 1;
+                const Site d3 = site_move(ra, x, nu, s);
+                const Site d2 = site_move(ra, d1, nu, s);
+                // raw links of the loop and which of them enter inverted
+                const mat3<T> l1 = ldU<T>(ra, nu, s > 0 ? d1 : d2);
+                const mat3<T> l2 = ldU<T>(ra, mu, d3);
+                const mat3<T> l3 = ldU<T>(ra, nu, s > 0 ? x : d3);
+                const mat3<T> l1a = m_adj(l1), l2a = m_adj(l2), l3a = m_adj(l3);
+                const mat3<T>& e1 = s > 0 ? l1 : l1a;
+                const mat3<T>& e1i = s > 0 ? l1a : l1;
+                const mat3<T>& e2 = l2a;
+                const mat3<T>& e2i = l2;
+                const mat3<T>& e3 = s > 0 ? l3a : l3;
+                const mat3<T>& e3i = s > 0 ? l3 : l3a;
+                if (!THETA) {
+                    const mat3<T> A = e1 * (e2 * e3);
+                    m_axpy(Lacc, cb, A);
+                    m_axpy(Racc, cb, m_adj(A));
+                } else {
+                    const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(P));
+                    const cx<T> cts = {sig * ct.re, sig * ct.im};
+                    const cx<T> mcts = {-cts.re, -cts.im};
+                    const mat3<T> X0 = load_mat(Fb, fo + p * ra.Vh + h, 6 * ra.V);
+                    const mat3<T> X1 = load_mat(Fb, fo + link_off(ra, 0, d1), 6 * ra.V);
+                    const mat3<T> X2 = load_mat(Fb, fo + link_off(ra, 0, d2), 6 * ra.V);
+                    const mat3<T> X3 = load_mat(Fb, fo + link_off(ra, 0, d3), 6 * ra.V);
+                    // forward chain
+                    mat3<T> I = X3 * e3;
+                    m_mac(I, e3, X0);
+                    mat3<T> Pm = e2 * e3;
+                    mat3<T> I2 = X2 * Pm;
+                    m_mac(I2, e2, I);
+                    Pm = e1 * Pm;
+                    I = X1 * Pm;
+                    m_mac(I, e1, I2);
+                    m_axpy(Lacc, cb, Pm);
+                    m_axpy(Lacc, cts, I);
+                    // backward chain
+                    mat3<T> J = X2 * e1i;
+                    m_mac(J, e1i, X1);
+                    mat3<T> Rm = e2i * e1i;
+                    mat3<T> J2 = X3 * Rm;
+                    m_mac(J2, e2i, J);
+                    Rm = e3i * Rm;
+                    J = X0 * Rm;
+                    m_mac(J, e3i, J2);
+                    m_axpy(Racc, cb, Rm);
+                    m_axpy(Racc, mcts, J);
+                }
+            }
+        }
+        const mat3<T> e0 = ldU<T>(ra, mu, x);
+        mat3<T> M = e0 * Lacc;
+        M = M - Racc * m_adj(e0);
+        const mat3<T> K = m_traceless(M);
+        store_mat((cx<T>*)ra.K, tid, 4 * ra.V, K);
+        kn2 = 0.5 * (double)m_norm2(K);
+        if (!isfinite(kn2)) kn2 = INFINITY;
+    }
+    double v[1] = {kn2};
+    block_reduce<1, true>(v, lds);
+    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_DRIFT])) {
+        const double km2 = gather_partials<true>(ra, KIND_LINK, 0, lds);
+        if (threadIdx.x == 0) {
+            Ctrl* c = ra.ctrl;
+            const double kmax = sqrt(km2);
+            double eps = ra.eps0;
+            if (ra.adaptive) {
+                if (c->bound <= 0.0) c->bound = ra.drift_bound > 0.0 ? ra.drift_bound : ra.eps0 * kmax;
+                if (kmax > 0.0 && c->bound / kmax < ra.eps0) eps = c->bound / kmax;
+            }
+            c->kmax = kmax;
+            c->eps = eps;
+            if (!isfinite(kmax)) c->status = ST_NONFINITE;
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// ---------------------------------------------------------------------------
+// Langevin update: U <- exp(i (eps K + sqrt(eps) eta_a lambda_a)) U, then
+// U <- U det(U)^{-1/3} in FP64.
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_LINK)
+    const Ctrl* cr = ra.ctrl;
+    const int ok = cr->status == ST_OK;
+    const double eps = cr->eps;
+    const int64_t step = cr->step;
+    double un = 0.0;
+    if (tid < 4 * ra.V && ok) {
+        int mu, p, h;
+        link_decompose(ra, tid, mu, p, h);
+        const Site s = site_coords(ra, p, h);
+        const uint32_t c0 = (uint32_t)(4 * site_lex(ra, s) + mu);
+        const T se = T(sqrt(eps) * 1.41421356237309504880);  // sqrt(eps) * sqrt(2)
+        T eta[8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) normal_pair<T>(ra.seed, c0, (uint32_t)step, (uint32_t)j, kStreamNoise,
+                                                   eta[2 * j], eta[2 * j + 1]);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) eta[a] *= se;
+        // A = i (eps K + H),  H = sum_a eta_a lambda_a (Hermitian)
+        const mat3<T> K = load_mat((const cx<T>*)ra.K, tid, 4 * ra.V);
+        const T r3 = T(0.57735026918962576451);
+        mat3<T> H;
+        H.e[0][0] = {eta[2] + r3 * eta[7], T(0)};
+        H.e[1][1] = {r3 * eta[7] - eta[2], T(0)};
+        H.e[2][2] = {T(-2) * r3 * eta[7], T(0)};
+        H.e[0][1] = {eta[0], -eta[1]};
+        H.e[1][0] = {eta[0], eta[1]};
+        H.e[0][2] = {eta[3], -eta[4]};
+        H.e[2][0] = {eta[3], eta[4]};
+        H.e[1][2] = {eta[5], -eta[6]};
+        H.e[2][1] = {eta[5], eta[6]};
+        const T te = T(eps);
+        mat3<T> A;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const cx<T> x = {fma(te, K.e[i][j].re, H.e[i][j].re), fma(te, K.e[i][j].im, H.e[i][j].im)};
+                A.e[i][j] = {-x.im, x.re};
+            }
+        const mat3<T> R = m_exp_traceless(A);
+        const mat3<T> U = load_mat((const cx<T>*)ra.U, tid, 4 * ra.V);
+        // det renormalisation in FP64 on the principal branch
+        const mat3<double> W = m_to_double(R * U);
+        const cx<double> d = m_det(W);
+        const double lr = -log(sqrt(fma(d.re, d.re, d.im * d.im))) / 3.0;
+        const double ph = -atan2(d.im, d.re) / 3.0;
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double mg = exp(lr);
+        const cx<double> w = {mg * cs, mg * sn};
+        const mat3<T> Un = m_cast_from<T>(m_scale(W, w));
+        store_mat((cx<T>*)ra.U, tid, 4 * ra.V, Un);
+        un = (double)m_norm2(Un);
+    }
+    double v[1] = {un};
+    block_reduce<1>(v, lds);
+    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_UPDATE])) {
+        const double tot = gather_partials(ra, KIND_LINK, 0, lds);
+        if (threadIdx.x == 0 && ok) {
+            Ctrl* c = ra.ctrl;
+            c->unorm = tot;
+            c->d_pre = tot / (12.0 * ra.V) - 1.0;
+            c->step = step + 1;
+            if (!isfinite(tot)) c->status = ST_NONFINITE;
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// ---------------------------------------------------------------------------
+// gauge cooling half-sweep
+//
+// Four lanes per site x of the active parity, lane mu owning U_mu(x) and
+// U_mu(x - mu): every link has exactly one end of each parity, so the
+// half-sweep reads and writes every link exactly once.  The lanes add their
+// share of G_x = sum_mu (U_mu(x) U_mu(x)^dagger - U_mu(x-mu)^dagger U_mu(x-mu))
+// with two quad shuffles; sum_a f_ax lambda_a = 4 G_x (G_x is traceless
+// Hermitian), so Omega_x = exp(-4 eps alpha G_x), a Hermitian matrix whose
+// exponential has real Cayley-Hamilton coefficients; Omega_x^{-1} =
+// exp(+4 eps alpha G_x) uses the same series with det -> -det.
+
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+
+// real Horner series for exp of a Hermitian traceless matrix (the Hermitian
+// counterpart of ch_exp_coeffs: s, t and the coefficients are real)
+template <typename T>
+__device__ __forceinline__ void ch_exp_coeffs_real(T s, T t, T& f0, T& f1, T& f2)
+{
+    T x = T(1), y = T(0), z = T(0);
+#pragma unroll
+    for (int n = exp_terms<T>::n; n >= 1; --n) {
+        const T inv = T(1) / T(n);
+        const T nx = t * z;
+        const T ny = fma(s, z, x);
+        const T nz = y;
+        x = fma(inv, nx, T(1));
+        y = inv * ny;
+        z = inv * nz;
+    }
+    f0 = x;
+    f1 = y;
+    f2 = z;
+}
+
+// E = exp(A), Ei = exp(-A) for Hermitian traceless A
+template <typename T>
+__device__ __forceinline__ void herm_exp_pair(const herm3<T>& A, mat3<T>& E, mat3<T>& Ei)
+{
+    mat3<T> Af = h_full(A);
+    const T fro2 = A.d0 * A.d0 + A.d1 * A.d1 + A.d2 * A.d2 +
+                   T(2) * (norm2(A.u01) + norm2(A.u02) + norm2(A.u12));
+    int k = 0;
+    if (fro2 > T(1)) {
+        k = (int)ceil(T(0.5) * log2(fro2));
+        const T sc = ldexp(T(1), -k);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Af.e[i][j] = sc * Af.e[i][j];
+    }
+    const mat3<T> A2 = Af * Af;
+    const T s = T(0.5) * (A2.e[0][0].re + A2.e[1][1].re + A2.e[2][2].re);
+    const T t = m_det(Af).re;
+    T f0, f1, f2, g0, g1, g2;
+    ch_exp_coeffs_real(s, t, f0, f1, f2);
+    ch_exp_coeffs_real(s, -t, g0, g1, g2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            E.e[i][j] = {fma(f1, Af.e[i][j].re, f2 * A2.e[i][j].re), fma(f1, Af.e[i][j].im, f2 * A2.e[i][j].im)};
+            Ei.e[i][j] = {fma(-g1, Af.e[i][j].re, g2 * A2.e[i][j].re), fma(-g1, Af.e[i][j].im, g2 * A2.e[i][j].im)};
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        E.e[i][i].re += f0;
+        Ei.e[i][i].re += g0;
+    }
+    for (int i = 0; i < k; ++i) {
+        E = E * E;
+        Ei = Ei * Ei;
+    }
+}
+
+template <typename T, int PAR>
+__global__ void __launch_bounds__(kBlock) k_cool(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+                                                 int iter)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_COOL)
+    Ctrl* cr = ra.ctrl;
+    // block-uniform: this run still cools in this iteration
+    if (iter < ra.n_cool && cr->status == ST_OK) {
+        double alpha_ad;
+        if (PAR == 0) {
+            alpha_ad = ra.mode == 1 ? ra.alpha / (cr->unorm / (4.0 * ra.V))
+                                    : (ra.mode == 2 ? cr->alpha_cur : ra.alpha);
+            if (lb == 0 && threadIdx.x == 0) {
+                if (ra.mode != 2) cr->alpha_cur = alpha_ad;
+                if (iter < kMaxCoolHist) {
+                    cr->hist_alpha[iter] = alpha_ad;
+                    cr->hist_un[iter] = cr->unorm;
+                    cr->hist_n = iter + 1;
+                }
+            }
+        } else {
+            alpha_ad = cr->alpha_cur;
+        }
+        const T coef = T(-4.0 * ra.eps_c * alpha_ad);
+        const int h = tid >> 2, mu = tid & 3;
+        const bool lane_ok = h < ra.Vh;
+        herm3<T> G = h_zero<T>();
+        mat3<T> Uf, Ub;
+        int of = 0, ob = 0;
+        const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
+        if (lane_ok) {
+            const Site x = site_coords(ra, PAR, h);
+            const Site xb = site_move(ra, x, mu, -1);
+            of = (mu * 2 + PAR) * ra.Vh + h;
+            ob = link_off(ra, mu, xb);
+            Uf = load_mat(Uc, of, 4 * ra.V);
+            Ub = load_mat(Uc, ob, 4 * ra.V);
+            h_add_uudag(G, Uf);
+            h_sub_udagu(G, Ub);
+        }
+        G.d0 = quad_sum(G.d0);
+        G.d1 = quad_sum(G.d1);
+        G.d2 = quad_sum(G.d2);
+        G.u01 = {quad_sum(G.u01.re), quad_sum(G.u01.im)};
+        G.u02 = {quad_sum(G.u02.re), quad_sum(G.u02.im)};
+        G.u12 = {quad_sum(G.u12.re), quad_sum(G.u12.im)};
+        double un = 0.0;
+        if (lane_ok) {
+            const T tr = (G.d0 + G.d1 + G.d2) * T(1.0 / 3.0);
+            herm3<T> A;
+            A.d0 = coef * (G.d0 - tr);
+            A.d1 = coef * (G.d1 - tr);
+            A.d2 = coef * (G.d2 - tr);
+            A.u01 = coef * G.u01;
+            A.u02 = coef * G.u02;
+            A.u12 = coef * G.u12;
+            mat3<T> E, Ei;
+            herm_exp_pair(A, E, Ei);
+            const mat3<T> Nf = E * Uf;
+            const mat3<T> Nb = Ub * Ei;
+            cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
+            store_mat(Uw, of, 4 * ra.V, Nf);
+            store_mat(Uw, ob, 4 * ra.V, Nb);
+            if (PAR == 1) un = (double)m_norm2(Nf) + (double)m_norm2(Nb);
+        }
+        if (PAR == 1) {
+            // every link is written exactly once by the odd half-sweep: the sum is
+            // the unitarity norm of the cooled configuration
+            double v[1] = {un};
+            block_reduce<1>(v, lds);
+            if (publish_partials(ra, KIND_COOL, lb, v, &cr->cnt[CNT_COOL])) {
+                const double tot = gather_partials(ra, KIND_COOL, 0, lds);
+                if (threadIdx.x == 0) {
+                    cr->unorm = tot;
+                    if (iter + 1 <= kMaxCoolHist) cr->hist_un[iter + 1] = tot;
+                    if (!isfinite(tot)) cr->status = ST_NONFINITE;
+                }
+            }
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// D_2 = mean over (a, x) of |f_ax| on the configuration entering a cooling
+// step, f_ax = 2 Tr(lambda_a G_x); sets alpha_cur = alpha / D_2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gradnorm(const BatchHdr* __restrict__ hdr,
+                                                     const RunArgs* __restrict__ runs, int iter)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_SITE)
+    Ctrl* cr = ra.ctrl;
+    if (ra.mode == 2 && iter < ra.n_cool && cr->status == ST_OK) {
+        double fs = 0.0;
+        if (tid < ra.V) {
+            const int p = tid >= ra.Vh;
+            const int h = tid - p * ra.Vh;
+            const Site x = site_coords(ra, p, h);
+            herm3<T> G = h_zero<T>();
+#pragma unroll 1
+            for (int mu = 0; mu < 4; ++mu) {
+                h_add_uudag(G, ldU<T>(ra, mu, x));
+                h_sub_udagu(G, ldU<T>(ra, mu, site_move(ra, x, mu, -1)));
+            }
+            const double r3 = 0.57735026918962576451;
+            fs = 4.0 * (fabs((double)G.u01.re) + fabs((double)G.u01.im) + fabs((double)G.u02.re) +
+                        fabs((double)G.u02.im) + fabs((double)G.u12.re) + fabs((double)G.u12.im)) +
+                 2.0 * fabs((double)G.d0 - (double)G.d1) +
+                 2.0 * r3 * fabs((double)G.d0 + (double)G.d1 - 2.0 * (double)G.d2);
+        }
+        double v[1] = {fs};
+        block_reduce<1>(v, lds);
+        if (publish_partials(ra, KIND_SITE, lb, v, &cr->cnt[CNT_GRAD])) {
+            const double tot = gather_partials(ra, KIND_SITE, 0, lds);
+            if (threadIdx.x == 0) {
+                const double D = tot / (8.0 * ra.V);
+                cr->alpha_cur = ra.alpha / D;
+                if (!(D > 0.0) || !isfinite(cr->alpha_cur)) cr->status = ST_NONFINITE;
+            }
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// ---------------------------------------------------------------------------
+// measurement: plaquette traces (and of their inverses, for the Wilson
+// action), topological charge density from the clover field, unitarity norm
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_measure(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+{
+    __shared__ double lds[7 * 4];
+    CLGC_FOR_BLOCKS(KIND_SITE)
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (tid < ra.V) {
+        const int p = tid >= ra.Vh;
+        const int h = tid - p * ra.Vh;
+        const Site x = site_coords(ra, p, h);
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            const mat3<T> Um = ldU<T>(ra, mu, x);
+            v[6] += (double)m_norm2(Um);
+#pragma unroll 1
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const mat3<T> Un = ldU<T>(ra, nu, x);
+                const mat3<T> Pm = (Um * ldU<T>(ra, nu, site_move(ra, x, mu, +1))) *
+                                   m_adj(Un * ldU<T>(ra, mu, site_move(ra, x, nu, +1)));
+                const cx<T> tp = m_tr(Pm);
+                const cx<T> ti = (Pm.e[1][1] * Pm.e[2][2] - Pm.e[1][2] * Pm.e[2][1]) +
+                                 (Pm.e[0][0] * Pm.e[2][2] - Pm.e[0][2] * Pm.e[2][0]) +
+                                 (Pm.e[0][0] * Pm.e[1][1] - Pm.e[0][1] * Pm.e[1][0]);
+                v[0] += (double)tp.re;
+                v[1] += (double)tp.im;
+                v[2] += (double)ti.re;
+                v[3] += (double)ti.im;
+            }
+        }
+        const cx<T>* __restrict__ Fb = (const cx<T>*)ra.F;
+        const int so = p * ra.Vh + h;
+        cx<double> q = {0.0, 0.0};
+#pragma unroll 1
+        for (int P = 0; P < 3; ++P) {
+            const cx<T> t = m_trmul(load_mat(Fb, P * ra.V + so, 6 * ra.V), load_mat(Fb, (5 - P) * ra.V + so, 6 * ra.V));
+            const double sg = P == 1 ? -1.0 : 1.0;
+            q.re += sg * (double)t.re;
+            q.im += sg * (double)t.im;
+        }
+        v[4] = q.re;
+        v[5] = q.im;
+    }
+    block_reduce<7>(v, lds);
+    if (publish_partials(ra, KIND_SITE, lb, v, &ra.ctrl->cnt[CNT_MEASURE])) {
+        for (int j = 0; j < 7; ++j) {
+            const double tot = gather_partials(ra, KIND_SITE, j, lds);
+            if (threadIdx.x == 0) ra.ctrl->obs[j] = tot;
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// ---------------------------------------------------------------------------
+// small control kernels (stream-ordered writes of host-side parameters)
+
+__global__ void k_write_args(RunArgs* dst, RunArgs src)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = src;
+}
+
+__global__ void k_write_state(Ctrl* c, int64_t step, double bound)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->step = step;
+        c->bound = bound;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+
+namespace {
+
+inline int grid_of(const Launch& L, int kind) { return L.blocks[kind] > 0 ? L.blocks[kind] : 1; }
+
+}  // namespace
+
+#define CLGC_LAUNCH(KERNEL, KIND, ...)                                                              \
+    hipLaunchKernelGGL(KERNEL, dim3(grid_of(L, KIND)), dim3(kBlock), 0, L.stream, L.hdr, L.runs, \
+                       ##__VA_ARGS__)
+
+hipError_t launch_init(const Launch& L, int prec, int perturbed, double sx, double sy)
+{
+    if (prec) CLGC_LAUNCH(k_init<float>, KIND_LINK, perturbed, sx, sy);
+    else CLGC_LAUNCH(k_init<double>, KIND_LINK, perturbed, sx, sy);
+    return hipGetLastError();
+}
+
+hipError_t launch_unorm(const Launch& L, int prec)
+{
+    if (prec) CLGC_LAUNCH(k_unorm<float>, KIND_LINK);
+    else CLGC_LAUNCH(k_unorm<double>, KIND_LINK);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Launch& L, int prec, const double* aos)
+{
+    if (prec) CLGC_LAUNCH(k_unpack<float>, KIND_LINK, aos);
+    else CLGC_LAUNCH(k_unpack<double>, KIND_LINK, aos);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos)
+{
+    if (prec) CLGC_LAUNCH(k_pack<float>, KIND_LINK, field, aos);
+    else CLGC_LAUNCH(k_pack<double>, KIND_LINK, field, aos);
+    return hipGetLastError();
+}
+
+hipError_t launch_clover(const Launch& L, int prec)
+{
+    if (prec) CLGC_LAUNCH(k_clover<float>, KIND_PLANE);
+    else CLGC_LAUNCH(k_clover<double>, KIND_PLANE);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(const Launch& L, int prec, bool theta)
+{
+    if (prec) {
+        if (theta) CLGC_LAUNCH((k_drift<float, true>), KIND_LINK);
+        else CLGC_LAUNCH((k_drift<float, false>), KIND_LINK);
+    } else {
+        if (theta) CLGC_LAUNCH((k_drift<double, true>), KIND_LINK);
+        else CLGC_LAUNCH((k_drift<double, false>), KIND_LINK);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const Launch& L, int prec)
+{
+    if (prec) CLGC_LAUNCH(k_update<float>, KIND_LINK);
+    else CLGC_LAUNCH(k_update<double>, KIND_LINK);
+    return hipGetLastError();
+}
+
+hipError_t launch_cool(const Launch& L, int prec, int parity, int iter)
+{
+    if (prec) {
+        if (parity) CLGC_LAUNCH((k_cool<float, 1>), KIND_COOL, iter);
+        else CLGC_LAUNCH((k_cool<float, 0>), KIND_COOL, iter);
+    } else {
+        if (parity) CLGC_LAUNCH((k_cool<double, 1>), KIND_COOL, iter);
+        else CLGC_LAUNCH((k_cool<double, 0>), KIND_COOL, iter);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gradnorm(const Launch& L, int prec, int iter)
+{
+    if (prec) CLGC_LAUNCH(k_gradnorm<float>, KIND_SITE, iter);
+    else CLGC_LAUNCH(k_gradnorm<double>, KIND_SITE, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const Launch& L, int prec)
+{
+    if (prec) CLGC_LAUNCH(k_measure<float>, KIND_SITE);
+    else CLGC_LAUNCH(k_measure<double>, KIND_SITE);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_write_args, dim3(1), dim3(64), 0, st, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_write_state, dim3(1), dim3(64), 0, st, c, step, bound);
+    return hipGetLastError();
+}
+
+}  // namespace clgc

@@ -1,0 +1,177 @@
+// lattice.hpp -- device data layout, run descriptors and index arithmetic.
+//
+// Link field in HBM ("complex-element SoA", checkerboard order):
+//   element e (0..8, row-major) of link (mu, parity p, half-index h) is the
+//   complex<T> at  U[e * 4V + (mu * 2 + p) * Vh + h],
+//   h = (x0 >> 1) + (L0/2) * (x1 + L1 * (x2 + L2 * x3)),  p = (x0+x1+x2+x3) & 1.
+// Consecutive lanes own consecutive h, so every load and store of one
+// matrix element by a wavefront is one contiguous 1 KB (FP64) or 512 B
+// (FP32) segment.  The drift field K uses the same layout; the clover field F
+// stores six planes per site: element e of plane P at site (p, h) is
+// F[e * 6V + P * V + p * Vh + h].
+//
+// Several independent runs (lattices of any even extents, each with its own
+// buffers and parameters) can share one launch: the logical blocks of all
+// runs are concatenated and a block finds its run by binary search in
+// BatchHdr::begin.  A single lattice is a batch of one.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "su3.hpp"
+
+namespace clgc {
+
+constexpr int kBlock = 256;        // threads per logical block, all kernels
+constexpr int kMaxRuns = 256;      // runs in one batched launch
+constexpr int kMaxCoolHist = 64;   // cooling steps per call kept in the history
+
+// logical-block kinds: what one thread owns
+enum Kind : int {
+    KIND_LINK = 0,   // one link: init, drift, update          (4V threads)
+    KIND_SITE = 1,   // one site: measurement                  (V threads)
+    KIND_COOL = 2,   // one (site of one parity, mu): cooling  (2V threads)
+    KIND_PLANE = 3,  // one (site, plane): clover field        (6V threads)
+    NKIND = 4
+};
+
+// reduction counters (one per reducing kernel)
+enum Counter : int { CNT_DRIFT = 0, CNT_UPDATE = 1, CNT_COOL = 2, CNT_MEASURE = 3, CNT_GRAD = 4, NCNT = 8 };
+
+enum Status : int { ST_OK = 0, ST_NONFINITE = 1 };
+
+// Per-run control block in device memory: everything the step-size and
+// cooling-strength control needs stays on the GPU between kernels.
+struct Ctrl {
+    double eps;         // step size of the last CL update
+    double bound;       // adaptive bound B (<= 0: not set)
+    double kmax;        // max ||Khat|| of the last drift
+    double unorm;       // sum Tr U U^dagger of the current links
+    double alpha_cur;   // alpha_ad of the cooling step in progress
+    double d_pre;       // distance after the last CL update
+    double obs[6];      // plaquette re/im, Q re/im, UN, (spare)
+    double hist_un[kMaxCoolHist + 1];
+    double hist_alpha[kMaxCoolHist];
+    int64_t step;       // CL step counter n (Philox counter word 1)
+    int32_t status;     // Status
+    int32_t hist_n;     // cooling steps recorded
+    uint32_t cnt[NCNT]; // last-block-done counters
+};
+
+// Per-run descriptor (device copy written by the host when it changes).
+struct RunArgs {
+    int L[4];
+    int Lh0;           // L0 / 2
+    int Vh;            // V / 2
+    int V;
+    int has_theta;
+    void* U;           // links, T = double or float
+    void* F;           // clover field
+    void* K;           // drift
+    double* part;      // per-logical-block partials: part[j * nblk + b]
+    Ctrl* ctrl;
+    double beta, th_re, th_im;
+    uint64_t seed;
+    double eps0, drift_bound;
+    int adaptive;
+    int mode;          // cl_alpha_mode
+    double eps_c, alpha;
+    int n_cool;        // cooling steps of the current call (batched: this run's own count)
+    int nblk[NKIND];   // logical blocks of this run per kind
+};
+
+struct BatchHdr {
+    int nrun;
+    int total[NKIND];
+    int begin[NKIND][kMaxRuns + 1];
+};
+
+// ---------------------------------------------------------------------------
+// index arithmetic
+
+struct Site {
+    int x[4];
+};
+
+__device__ __forceinline__ Site site_coords(const RunArgs& ra, int p, int h)
+{
+    Site s;
+    int r = h / ra.Lh0;
+    const int x0h = h - r * ra.Lh0;
+    int q = r / ra.L[1];
+    s.x[1] = r - q * ra.L[1];
+    r = q;
+    q = r / ra.L[2];
+    s.x[2] = r - q * ra.L[2];
+    s.x[3] = q;
+    s.x[0] = 2 * x0h + ((p + s.x[1] + s.x[2] + s.x[3]) & 1);
+    return s;
+}
+
+__device__ __forceinline__ int site_half(const RunArgs& ra, const Site& s)
+{
+    return (s.x[0] >> 1) + ra.Lh0 * (s.x[1] + ra.L[1] * (s.x[2] + ra.L[2] * s.x[3]));
+}
+
+__device__ __forceinline__ int site_parity(const Site& s) { return (s.x[0] + s.x[1] + s.x[2] + s.x[3]) & 1; }
+
+__device__ __forceinline__ int site_lex(const RunArgs& ra, const Site& s)
+{
+    return s.x[0] + ra.L[0] * (s.x[1] + ra.L[1] * (s.x[2] + ra.L[2] * s.x[3]));
+}
+
+// s + d * mu_hat with periodic wrap, |d| <= 2
+__device__ __forceinline__ Site site_move(const RunArgs& ra, Site s, int mu, int d)
+{
+    int v = s.x[mu] + d;
+    const int L = ra.L[mu];
+    v = v >= L ? v - L : v;
+    v = v < 0 ? v + L : v;
+    s.x[mu] = v;
+    return s;
+}
+
+// offset (in complex elements, without the e * 4V term) of link (mu, site)
+__device__ __forceinline__ int link_off(const RunArgs& ra, int mu, const Site& s)
+{
+    return (mu * 2 + site_parity(s)) * ra.Vh + site_half(ra, s);
+}
+
+template <typename T>
+__device__ __forceinline__ mat3<T> load_mat(const cx<T>* __restrict__ base, int off, int stride)
+{
+    mat3<T> m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m.e[e / 3][e % 3] = base[e * stride + off];
+    return m;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_mat(cx<T>* __restrict__ base, int off, int stride, const mat3<T>& m)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) base[e * stride + off] = m.e[e / 3][e % 3];
+}
+
+// dual clover partner of plane P (0..5 = 01,02,03,12,13,23) and its sign:
+// Ft01 = F23, Ft02 = -F13, Ft03 = F12, Ft12 = F03, Ft13 = -F02, Ft23 = F01.
+__host__ __device__ constexpr int plane_of(int mu, int nu)
+{
+    return mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
+}
+__host__ __device__ constexpr int dual_plane(int P) { return 5 - P; }
+__host__ __device__ constexpr int dual_sign(int P) { return (P == 1 || P == 4) ? -1 : 1; }
+
+// find the run that owns logical block b of a kind (uniform per block)
+__device__ __forceinline__ int find_run(const BatchHdr* __restrict__ hdr, int kind, int b)
+{
+    int lo = 0, hi = hdr->nrun - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (hdr->begin[kind][mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace clgc

@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark: complex Langevin + adaptive gauge cooling link-updates/s on one
+MI355X.
+
+Workload (the paper's SU(3) + theta-term method at the 16^4 production size):
+16^4 periodic lattice, beta = 6.0, theta = 1.0, seed 3, perturbed SL(3,C)
+start, adaptive Langevin step (eps0 = 1e-2, bound fixed on the first step),
+10 adaptive (D_1) gauge-cooling steps with alpha = 1 and eps_c = eps0 after
+every update.  One "step" = one CL update of every link + its 10 cooling
+steps.  value = 4 V x steps / wall time (link-updates/s), with the links
+resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  Also reports the mixed-precision path on the same
+workload, the dominant kernel's roofline (average duration from HIP events
+recorded around every launch of the timed region) and the FP64 CPU oracle
+timed on a bounded sample (2 steps) of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CL+cooling link-updates/s at 16^4, FP64 vs mixed; served p50/p99 step latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_FP64_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+VALU_FP32_TFLOPS = 78.6        # same rate: packed FP32 instructions are disabled in this build
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1311_1056_amd", "csrc", "kernels.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dims", default="16,16,16,16")
+    ap.add_argument("--theta", type=float, default=1.0)
+    ap.add_argument("--beta", type=float, default=6.0)
+    ap.add_argument("--ncool", type=int, default=10)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_src_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_cost(kind, V, rs, theta):
+    """Algorithmic bytes and flops of one launch (roofline section).
+
+    Bytes: the compulsory HBM traffic (each field element read / written once).
+    Flops: 3x3 complex product = 108 FMA = 216 flops, adjugate = 9 x 2 complex
+    multiplies + 9 complex subtractions = 126 flops."""
+    L = 4 * V
+    mat = 18 * rs
+    prod, adj = 216, 126
+    if kind in ("cool_even", "cool_odd"):
+        # every link read and written once; per site: G (8 Hermitian products of 54 flops),
+        # two Hermitian exponentials (~2 x 400), 8 link products
+        return {"bytes": L * 2 * mat, "flops": (V // 2) * (8 * 54 + 800 + 8 * prod)}
+    if kind == "drift":
+        wil = 6 * (2 * prod + adj) + 2 * prod + adj
+        top = 6 * (14 * prod + 2 * adj) if theta else 0
+        byt = L * (mat + mat) + (V * 6 * mat if theta else 0)  # links + K out (+ F in)
+        return {"bytes": byt, "flops": L * (wil + top)}
+    if kind == "update":
+        return {"bytes": L * 3 * mat, "flops": L * (3 * prod + 600)}
+    if kind == "clover":
+        return {"bytes": L * mat + V * 6 * mat, "flops": V * 6 * (12 * prod + 8 * adj)}
+    return None
+
+
+def run_gpu(args, precision, with_timing=True):
+    import torch
+    import paper_1311_1056_amd as cl
+    dims = tuple(int(x) for x in args.dims.split(","))
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    prec = cl.CL_FP64 if precision == "fp64" else cl.CL_MIXED
+    lat = cl.Lattice(dims, args.beta, args.theta, prec, seed=3, device="cuda:0")
+    lat.init(True, 0.3, 0.05)
+    kw = dict(eps0=1e-2, adaptive=True, n_cool=args.ncool, eps_c=1e-2, alpha=1.0, mode=cl.CL_ALPHA_UNORM)
+    lat.run_steps(args.warmup, **kw)
+    torch.cuda.synchronize()
+    if with_timing:
+        lat.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.run_steps(args.steps, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = lat.timing_read() if with_timing else {}
+    lat.timing_enable(False)
+    obs = lat.measure()
+    lat.close()
+    dt = t1 - t0
+    return {"V": V, "dims": dims, "seconds": dt, "ms_per_step": 1e3 * dt / args.steps,
+            "value": 4 * V * args.steps / dt, "timing": timing, "obs": obs}
+
+
+def roofline(res, precision, theta):
+    rs = 8 if precision == "fp64" else 4
+    V = res["V"]
+    timing = res["timing"]
+    if not timing:
+        return None, {}
+    total = sum(ms for ms, _ in timing.values())
+    kernels = {}
+    for k, (ms, n) in timing.items():
+        c = algorithmic_cost(k, V, rs, theta)
+        ent = {"avg_us": 1e3 * ms / n, "launches": n, "share": ms / total}
+        if c:
+            t = ms / n * 1e-3
+            ent["alg_GBs"] = c["bytes"] / t / 1e9
+            ent["alg_TFLOPs"] = c["flops"] / t / 1e12
+        kernels[k] = ent
+    # the dominant kernel: the cooling sweep (both parities are one kernel)
+    groups = {}
+    for k, (ms, n) in timing.items():
+        g = "cool" if k.startswith("cool") else k
+        a = groups.setdefault(g, [0.0, 0])
+        a[0] += ms
+        a[1] += n
+    dom = max(groups, key=lambda g: groups[g][0])
+    ms, n = groups[dom]
+    t = ms / n * 1e-3
+    c = algorithmic_cost("cool_even" if dom == "cool" else dom, V, rs, theta)
+    peak_flops = VALU_FP64_TFLOPS if precision == "fp64" else VALU_FP32_TFLOPS
+    if dom == "cool" or c["flops"] / c["bytes"] < peak_flops * 1e12 / (HBM_PEAK_GBS * 1e9):
+        achieved = c["bytes"] / t / 1e9
+        rf = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    else:
+        achieved = c["flops"] / t / 1e12
+        rf = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak_flops, "unit": "TFLOP/s",
+              "frac": round(achieved / peak_flops, 4)}
+    rf["kernel"] = "k_cool" if dom == "cool" else "k_" + dom
+    rf["avg_us"] = round(1e6 * t, 2)
+    rf["share_of_step"] = round(ms / total, 3)
+    rf["traffic"] = traffic_for(rf["kernel"], precision, res["dims"])
+    return rf, kernels
+
+
+def traffic_for(kernel, precision, dims):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    key = f"{kernel}/{precision}/{'x'.join(map(str, dims))}"
+    ent = tab.get(key)
+    if not ent or ent.get("src_sha") != kernel_src_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(args):
+    import numpy as np
+    import oracle
+    dims = tuple(int(x) for x in args.dims.split(","))
+    V = int(np.prod(dims))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    U = oracle.init_links(dims, 3, 0.3, 0.05)
+    t0 = time.perf_counter()
+    oracle.run(dims, U, args.beta, args.theta, 3, args.cpu_steps, 1e-2, True, args.ncool, 1e-2, 1.0, 1)
+    dt = time.perf_counter() - t0
+    return {"value": 4 * V * args.cpu_steps / dt, "unit": "link-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{args.cpu_steps} steps (CL update + {args.ncool} cooling steps + measurement each) of the "
+                      f"same {'x'.join(map(str, dims))} workload, FP64, {threads} OpenMP threads, {dt:.1f} s"}
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}), flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "independent runs shard across GPUs with no exchange, so the per-GPU figure is the N=1 line",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+        return
+    res = run_gpu(args, args.precision)
+    rf, kernels = roofline(res, args.precision, args.theta)
+    out = {
+        "metric": METRIC,
+        "value": round(res["value"], 1),
+        "unit": "link-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"CL + adaptive gauge cooling, SU(3) Wilson + theta, {args.dims.replace(',', 'x')} "
+                               f"periodic, beta={args.beta}, theta={args.theta}, seed 3, adaptive eps0=1e-2, "
+                               f"{args.ncool} D1 cooling steps (alpha=1, eps_c=1e-2) per update",
+                   "lattice": args.dims.replace(",", "x"), "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": rf,
+        "kernels": kernels,
+        "observables_after": {"plaq": [res["obs"]["plaq"].real, res["obs"]["plaq"].imag],
+                              "q": [res["obs"]["q"].real, res["obs"]["q"].imag], "d": res["obs"]["d"]},
+    }
+    if args.precision == "fp64" and not args.no_mixed:
+        mx = run_gpu(args, "mixed")
+        mrf, mk = roofline(mx, "mixed", args.theta)
+        out["mixed"] = {"value": round(mx["value"], 1), "ms_per_step": round(mx["ms_per_step"], 4),
+                        "dtype": "f32 links/drift/cooling, f64 det renorm, reductions and control",
+                        "roofline": mrf}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,22 @@ cl_status cl_cool_history(cl_lattice* lat, double* unorm, double* alpha, int cap
 cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_desc* cool,
                        int n_steps);
 
+/* Kernel kinds reported by cl_timing_read. */
+typedef enum {
+    CL_K_INIT = 0, CL_K_UNORM = 1, CL_K_PACK = 2, CL_K_CLOVER = 3, CL_K_DRIFT = 4, CL_K_UPDATE = 5,
+    CL_K_COOL_EVEN = 6, CL_K_COOL_ODD = 7, CL_K_GRADNORM = 8, CL_K_MEASURE = 9, CL_K_COUNT = 10
+} cl_kernel_kind;
+
+/* Benchmark instrumentation: while enabled, every kernel the lattice
+ * launches is bracketed by a pair of HIP events on its stream.  Disabled by
+ * default.  Enabling clears the previous record. */
+cl_status cl_timing_enable(cl_lattice* lat, int enable);
+
+/* Waits for the stream, then gives per kernel kind (cap >= CL_K_COUNT
+ * entries) the summed event-measured milliseconds and launch count recorded
+ * since cl_timing_enable(lat, 1). */
+cl_status cl_timing_read(cl_lattice* lat, double* total_ms, int64_t* launches, int cap);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* cl_last_error(void);
 

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libclgc.so")
 CL_OK, CL_EINVAL, CL_ENOMEM, CL_EHIP, CL_ENONFINITE, CL_EBUDGET = 0, -1, -2, -3, -4, -5
 CL_FP64, CL_MIXED = 0, 1
 CL_ALPHA_FIXED, CL_ALPHA_UNORM, CL_ALPHA_GRAD = 0, 1, 2
+KERNEL_KINDS = ("init", "unorm", "pack", "clover", "drift", "update", "cool_even", "cool_odd", "gradnorm",
+                "measure")
 
 
 class cl_lattice_desc(ctypes.Structure):
@@ -74,6 +76,8 @@ def _load():
         "cl_compute_drift": [vp, dp, sz],
         "cl_cool_history": [vp, dp, dp, ctypes.c_int, P(ctypes.c_int)],
         "cl_run_steps": [vp, P(cl_step_desc), P(cl_cool_desc), ctypes.c_int],
+        "cl_timing_enable": [vp, ctypes.c_int],
+        "cl_timing_read": [vp, dp, P(ctypes.c_int64), ctypes.c_int],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -220,3 +224,14 @@ class Lattice:
         n = ctypes.c_int()
         _check(lib.cl_cool_history(self.handle, _dp(un), _dp(al), 65, ctypes.byref(n)))
         return un[:n.value + 1], al[:n.value]
+
+    def timing_enable(self, on=True):
+        _check(lib.cl_timing_enable(self.handle, int(on)))
+
+    def timing_read(self):
+        """{kernel kind: (total ms, launches)} since timing_enable(True)."""
+        n = len(KERNEL_KINDS)
+        ms = np.zeros(n)
+        cnt = (ctypes.c_int64 * n)()
+        _check(lib.cl_timing_read(self.handle, _dp(ms), cnt, n))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS) if cnt[i]}

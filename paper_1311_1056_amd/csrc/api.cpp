@@ -110,9 +110,56 @@ struct cl_lattice {
     Launch L;
     bool F_valid;      // clover field matches the current links
     bool has_theta;
+    // benchmark instrumentation (cl_timing_enable)
+    bool timing;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace {
+
+hipEvent_t take_event(cl_lattice* lat)
+{
+    if (!lat->pool.empty()) {
+        hipEvent_t e = lat->pool.back();
+        lat->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void recycle_marks(cl_lattice* lat)
+{
+    for (auto& m : lat->marks) {
+        lat->pool.push_back(m.a);
+        lat->pool.push_back(m.b);
+    }
+    lat->marks.clear();
+}
+
+// launch `expr` (a hipError_t-returning launcher) bracketed by timing events
+// when the lattice records timings
+#define TIMED(lat, KIND, expr)                                                        \
+    do {                                                                              \
+        hipEvent_t ea_ = nullptr, eb_ = nullptr;                                      \
+        if ((lat)->timing) {                                                          \
+            ea_ = take_event(lat);                                                    \
+            eb_ = take_event(lat);                                                    \
+            if (!ea_ || !eb_) return fail(CL_EHIP, "hipEventCreate failed");         \
+            HIP_TRY(hipEventRecord(ea_, (lat)->stream));                              \
+        }                                                                             \
+        HIP_TRY(expr);                                                                \
+        if ((lat)->timing) {                                                          \
+            HIP_TRY(hipEventRecord(eb_, (lat)->stream));                              \
+            (lat)->marks.push_back({(KIND), ea_, eb_});                               \
+        }                                                                             \
+    } while (0)
 
 cl_status push_args(cl_lattice* lat)
 {
@@ -189,9 +236,9 @@ void soa_to_host(const cl_lattice* lat, const void* raw, double* host)
 cl_status enqueue_step(cl_lattice* lat)
 {
     const bool theta = lat->has_theta;
-    if (theta && !lat->F_valid) HIP_TRY(launch_clover(lat->L, lat->prec));
-    HIP_TRY(launch_drift(lat->L, lat->prec, theta));
-    HIP_TRY(launch_update(lat->L, lat->prec));
+    if (theta && !lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec));
+    TIMED(lat, CL_K_DRIFT, launch_drift(lat->L, lat->prec, theta));
+    TIMED(lat, CL_K_UPDATE, launch_update(lat->L, lat->prec));
     lat->F_valid = false;
     return CL_OK;
 }
@@ -199,9 +246,9 @@ cl_status enqueue_step(cl_lattice* lat)
 cl_status enqueue_cool(cl_lattice* lat, int n)
 {
     for (int i = 0; i < n; ++i) {
-        if (lat->args.mode == CL_ALPHA_GRAD) HIP_TRY(launch_gradnorm(lat->L, lat->prec, i));
-        HIP_TRY(launch_cool(lat->L, lat->prec, 0, i));
-        HIP_TRY(launch_cool(lat->L, lat->prec, 1, i));
+        if (lat->args.mode == CL_ALPHA_GRAD) TIMED(lat, CL_K_GRADNORM, launch_gradnorm(lat->L, lat->prec, i));
+        TIMED(lat, CL_K_COOL_EVEN, launch_cool(lat->L, lat->prec, 0, i));
+        TIMED(lat, CL_K_COOL_ODD, launch_cool(lat->L, lat->prec, 1, i));
     }
     if (n > 0) lat->F_valid = false;
     return CL_OK;
@@ -305,6 +352,8 @@ cl_status cl_lattice_destroy(cl_lattice* lat)
 {
     if (!lat) return fail(CL_EINVAL, "lattice is NULL");
     hipError_t e = hipStreamSynchronize(lat->stream);
+    recycle_marks(lat);
+    for (hipEvent_t ev : lat->pool) (void)hipEventDestroy(ev);
     delete lat;
     if (e != hipSuccess) return fail(CL_EHIP, "cl_lattice_destroy: %s", hipGetErrorString(e));
     return CL_OK;
@@ -425,9 +474,9 @@ cl_status cl_unitarity_norm(cl_lattice* lat, double* d)
 cl_status cl_measure(cl_lattice* lat, cl_obs* out)
 {
     if (!lat || !out) return fail(CL_EINVAL, "NULL argument");
-    if (!lat->F_valid) HIP_TRY(launch_clover(lat->L, lat->prec));
+    if (!lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec));
     lat->F_valid = true;
-    HIP_TRY(launch_measure(lat->L, lat->prec));
+    TIMED(lat, CL_K_MEASURE, launch_measure(lat->L, lat->prec));
     Ctrl c;
     cl_status st = read_ctrl(lat, &c);
     if (st) return st;
@@ -476,6 +525,33 @@ cl_status cl_compute_drift(cl_lattice* lat, double* host_K, size_t n_doubles)
     HIP_TRY(hipMemcpyAsync(lat->d_ctrl, &saved, sizeof saved, hipMemcpyHostToDevice, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     soa_to_host(lat, raw.data(), host_K);
+    return CL_OK;
+}
+
+cl_status cl_timing_enable(cl_lattice* lat, int enable)
+{
+    if (!lat) return fail(CL_EINVAL, "lattice is NULL");
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    recycle_marks(lat);
+    lat->timing = enable != 0;
+    return CL_OK;
+}
+
+cl_status cl_timing_read(cl_lattice* lat, double* total_ms, int64_t* launches, int cap)
+{
+    if (!lat || !total_ms || !launches) return fail(CL_EINVAL, "NULL argument");
+    if (cap < CL_K_COUNT) return fail(CL_EINVAL, "cap must be >= %d", (int)CL_K_COUNT);
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    for (int k = 0; k < cap; ++k) {
+        total_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (const auto& m : lat->marks) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, m.a, m.b));
+        total_ms[m.kind] += ms;
+        launches[m.kind] += 1;
+    }
     return CL_OK;
 }
 

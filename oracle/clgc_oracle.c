@@ -523,13 +523,17 @@ double orc_unitarity_norm(const int *dims, const double *links)
  * for mu < nu: Ft01 = F23, Ft02 = -F13, Ft03 = F12, Ft12 = F03,
  * Ft13 = -F02, Ft23 = F01, so that sum_P Tr(F_P Ft_P) is twice the bracket
  * of the clover form of q_L. */
-static M3 dual_clover(const M3 *F, long s, int mu, int nu)
+static M3 dual_clover(const Geom *g, const double *links, const M3 *F, long s, int mu, int nu)
 {
     int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
     int p = plane_index(a, b);
     static const int partner[6] = {5, 4, 3, 2, 1, 0};
+    static const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
     static const double sgn[6] = {+1, -1, +1, +1, -1, +1};
-    return m_scale(F[s * 6 + partner[p]], sgn[p]);
+    int q = partner[p];
+    /* from the precomputed field, or evaluated at this site when F is NULL */
+    M3 f = F ? F[s * 6 + q] : clover(g, links, s, pa[q], pb[q]);
+    return m_scale(f, sgn[p]);
 }
 
 /* Drift Khat = sum_a K_a lambda_a of link (s, mu), K_a = -D_a S,
@@ -551,7 +555,7 @@ static M3 dual_clover(const M3 *F, long s, int mu, int nu)
  * of e0^{-1}, in every clover leaf that contains the link) is checked
  * against central finite differences of S_W and Q_L in the tests. */
 static M3 link_drift(const Geom *g, const double *links, const M3 *F, long s, int mu,
-                     double beta, cplx theta)
+                     double beta, cplx theta, int with_theta)
 {
     M3 wil = m_zero(), top = m_zero();
     for (int nu = 0; nu < 4; ++nu) {
@@ -564,12 +568,12 @@ static M3 link_drift(const Geom *g, const double *links, const M3 *F, long s, in
             for (int k = 0; k < 4; ++k) { d[k] = cur; e[k] = hop(g, links, &cur, dirs[k]); }
             M3 gam = m_mul(m_mul(e[0], e[1]), m_mul(e[2], e[3]));
             wil = m_add(wil, m_sub(gam, m_inv(gam)));
-            if (F) {
+            if (with_theta) {
                 double sigma = sg * (nu > mu ? 1.0 : -1.0);
                 M3 ei[4];
                 for (int k = 0; k < 4; ++k) ei[k] = m_inv(e[k]);
                 M3 X[4];
-                for (int k = 0; k < 4; ++k) X[k] = dual_clover(F, d[k], mu, nu);
+                for (int k = 0; k < 4; ++k) X[k] = dual_clover(g, links, F, d[k], mu, nu);
                 M3 acc = m_zero();
                 /* Lam_k: X_k inserted at corner d_k of e0 e1 e2 e3 */
                 acc = m_add(acc, m_mul(gam, X[0]));
@@ -586,7 +590,7 @@ static M3 link_drift(const Geom *g, const double *links, const M3 *F, long s, in
         }
     }
     M3 K = m_scale(m_tl(wil), I * beta / 3.0);
-    if (F) K = m_add(K, m_scale(m_tl(top), theta / (128.0 * M_PI * M_PI)));
+    if (with_theta) K = m_add(K, m_scale(m_tl(top), theta / (128.0 * M_PI * M_PI)));
     return K;
 }
 
@@ -600,21 +604,22 @@ void orc_drift(const int *dims, const double *links, double beta, double theta_r
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < g.V; ++s)
         for (int mu = 0; mu < 4; ++mu)
-            set_link(K, s, mu, link_drift(&g, links, F, s, mu, beta, theta));
+            set_link(K, s, mu, link_drift(&g, links, F, s, mu, beta, theta, F != NULL));
     free(F);
 }
 
-/* Drift of selected links only (for sampled checks on large lattices). */
+/* Drift of selected links only (for sampled checks on large lattices); the
+ * clover matrices are evaluated where the selected links need them. */
 void orc_drift_links(const int *dims, const double *links, double beta, double theta_re,
                      double theta_im, const long *sel, long nsel, double *K)
 {
     Geom g = geom(dims);
     cplx theta = theta_re + I * theta_im;
-    M3 *F = (theta_re != 0.0 || theta_im != 0.0) ? clover_field(&g, links) : NULL;
+    int with_theta = theta_re != 0.0 || theta_im != 0.0;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < nsel; ++i)
-        put_mat(K + 18 * i, link_drift(&g, links, F, sel[i] / 4, (int)(sel[i] % 4), beta, theta));
-    free(F);
+        put_mat(K + 18 * i, link_drift(&g, links, NULL, sel[i] / 4, (int)(sel[i] % 4), beta, theta,
+                                       with_theta));
 }
 
 /* ||Khat||^2 = (1/2) Tr(Khat Khat^dagger) = sum_a |K_a|^2. */

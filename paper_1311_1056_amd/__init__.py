@@ -23,7 +23,7 @@ CL_OK, CL_EINVAL, CL_ENOMEM, CL_EHIP, CL_ENONFINITE, CL_EBUDGET = 0, -1, -2, -3,
 CL_FP64, CL_MIXED = 0, 1
 CL_ALPHA_FIXED, CL_ALPHA_UNORM, CL_ALPHA_GRAD = 0, 1, 2
 KERNEL_KINDS = ("init", "unorm", "pack", "clover", "drift", "update", "cool_even", "cool_odd", "gradnorm",
-                "measure")
+                "measure", "finalize")
 
 
 class cl_lattice_desc(ctypes.Structure):

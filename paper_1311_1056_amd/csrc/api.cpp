@@ -118,6 +118,10 @@ struct cl_lattice {
     };
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
+    // one captured CL step (update + cooling), replayed by cl_run_steps
+    hipStream_t cap_stream;
+    hipGraphExec_t step_graph;
+    int graph_key[3];   // n_cool, mode, has_theta of the captured step
 };
 
 namespace {
@@ -238,7 +242,9 @@ cl_status enqueue_step(cl_lattice* lat)
     const bool theta = lat->has_theta;
     if (theta && !lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec));
     TIMED(lat, CL_K_DRIFT, launch_drift(lat->L, lat->prec, theta));
+    TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_DRIFT, 0));
     TIMED(lat, CL_K_UPDATE, launch_update(lat->L, lat->prec));
+    TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_UPDATE, 0));
     lat->F_valid = false;
     return CL_OK;
 }
@@ -246,11 +252,57 @@ cl_status enqueue_step(cl_lattice* lat)
 cl_status enqueue_cool(cl_lattice* lat, int n)
 {
     for (int i = 0; i < n; ++i) {
-        if (lat->args.mode == CL_ALPHA_GRAD) TIMED(lat, CL_K_GRADNORM, launch_gradnorm(lat->L, lat->prec, i));
+        if (lat->args.mode == CL_ALPHA_GRAD) {
+            TIMED(lat, CL_K_GRADNORM, launch_gradnorm(lat->L, lat->prec, i));
+            TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_GRAD, i));
+        }
         TIMED(lat, CL_K_COOL_EVEN, launch_cool(lat->L, lat->prec, 0, i));
         TIMED(lat, CL_K_COOL_ODD, launch_cool(lat->L, lat->prec, 1, i));
+        TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_COOL, i));
     }
     if (n > 0) lat->F_valid = false;
+    return CL_OK;
+}
+
+// Capture one full step (drift, update, n_cool cooling steps and their
+// finalize kernels) into a graph.  Kernels read every parameter from the
+// device RunArgs / Ctrl, so the graph stays valid while parameters change;
+// only the launch sequence (n_cool, D_2 mode, theta) keys it.
+cl_status ensure_step_graph(cl_lattice* lat, int n_cool)
+{
+    const int key[3] = {n_cool, lat->args.mode, lat->has_theta ? 1 : 0};
+    if (lat->step_graph && std::memcmp(key, lat->graph_key, sizeof key) == 0) return CL_OK;
+    if (lat->step_graph) {
+        HIP_TRY(hipGraphExecDestroy(lat->step_graph));
+        lat->step_graph = nullptr;
+    }
+    if (!lat->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&lat->cap_stream, hipStreamNonBlocking));
+    const hipStream_t user = lat->stream;
+    lat->stream = lat->cap_stream;
+    lat->L.stream = lat->cap_stream;
+    lat->F_valid = false;  // every replayed step rebuilds the clover field
+    hipGraph_t g = nullptr;
+    cl_status st = CL_OK;
+    hipError_t e = hipStreamBeginCapture(lat->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue_step(lat);
+        if (st == CL_OK) st = enqueue_cool(lat, n_cool);
+        e = hipStreamEndCapture(lat->cap_stream, &g);
+    }
+    lat->stream = user;
+    lat->L.stream = user;
+    lat->F_valid = false;
+    if (st != CL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(CL_EHIP, "stream capture of a CL step: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    lat->step_graph = ex;
+    std::memcpy(lat->graph_key, key, sizeof key);
     return CL_OK;
 }
 
@@ -327,6 +379,7 @@ cl_status cl_lattice_create(const cl_lattice_desc* desc, void* dev_buf, size_t b
     lat->L.hdr = lat->d_hdr;
     lat->L.runs = lat->d_args;
     for (int k = 0; k < NKIND; ++k) lat->L.blocks[k] = a.nblk[k];
+    lat->L.nrun = 1;
     lat->L.stream = lat->stream;
 
     hipError_t e = hipMemcpyAsync(lat->d_hdr, &hdr, sizeof hdr, hipMemcpyHostToDevice, lat->stream);
@@ -354,6 +407,8 @@ cl_status cl_lattice_destroy(cl_lattice* lat)
     hipError_t e = hipStreamSynchronize(lat->stream);
     recycle_marks(lat);
     for (hipEvent_t ev : lat->pool) (void)hipEventDestroy(ev);
+    if (lat->step_graph) (void)hipGraphExecDestroy(lat->step_graph);
+    if (lat->cap_stream) (void)hipStreamDestroy(lat->cap_stream);
     delete lat;
     if (e != hipSuccess) return fail(CL_EHIP, "cl_lattice_destroy: %s", hipGetErrorString(e));
     return CL_OK;
@@ -365,6 +420,7 @@ cl_status cl_lattice_init(cl_lattice* lat, int perturbed, double sigma_x, double
     if (perturbed && (!std::isfinite(sigma_x) || !std::isfinite(sigma_y)))
         return fail(CL_EINVAL, "sigma must be finite");
     HIP_TRY(launch_init(lat->L, lat->prec, perturbed ? 1 : 0, sigma_x, sigma_y));
+    HIP_TRY(launch_finalize(lat->L, FIN_INIT, 0));
     lat->F_valid = false;
     return CL_OK;
 }
@@ -378,6 +434,7 @@ cl_status cl_lattice_set_links(cl_lattice* lat, const double* host, size_t n_dou
     HIP_TRY(hipMemcpyAsync(stage, host, n * sizeof(double), hipMemcpyHostToDevice, lat->stream));
     HIP_TRY(launch_unpack(lat->L, lat->prec, stage));
     HIP_TRY(launch_unorm(lat->L, lat->prec));
+    HIP_TRY(launch_finalize(lat->L, FIN_UNORM, 0));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     lat->F_valid = false;
     return CL_OK;
@@ -453,10 +510,18 @@ cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_
     cl_status st = set_step_params(lat, step);
     if (st) return st;
     if ((st = set_cool_params(lat, cool)) != CL_OK) return st;
-    for (int i = 0; i < n_steps; ++i) {
-        if ((st = enqueue_step(lat)) != CL_OK) return st;
-        if ((st = enqueue_cool(lat, cool->n_steps)) != CL_OK) return st;
+    if (n_steps == 0) return CL_OK;
+    if (lat->timing) {
+        // instrumented path: individual launches bracketed by events
+        for (int i = 0; i < n_steps; ++i) {
+            if ((st = enqueue_step(lat)) != CL_OK) return st;
+            if ((st = enqueue_cool(lat, cool->n_steps)) != CL_OK) return st;
+        }
+        return CL_OK;
     }
+    if ((st = ensure_step_graph(lat, cool->n_steps)) != CL_OK) return st;
+    for (int i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(lat->step_graph, lat->stream));
+    lat->F_valid = false;
     return CL_OK;
 }
 
@@ -477,6 +542,7 @@ cl_status cl_measure(cl_lattice* lat, cl_obs* out)
     if (!lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec));
     lat->F_valid = true;
     TIMED(lat, CL_K_MEASURE, launch_measure(lat->L, lat->prec));
+    TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_MEASURE, 0));
     Ctrl c;
     cl_status st = read_ctrl(lat, &c);
     if (st) return st;
@@ -517,6 +583,7 @@ cl_status cl_compute_drift(cl_lattice* lat, double* host_K, size_t n_doubles)
     if (lat->has_theta && !lat->F_valid) HIP_TRY(launch_clover(lat->L, lat->prec));
     lat->F_valid = lat->has_theta;
     HIP_TRY(launch_drift(lat->L, lat->prec, lat->has_theta));
+    HIP_TRY(launch_finalize(lat->L, FIN_DRIFT, 0));
     // raw SoA copy of the drift, reordered on the host
     const size_t rs = lat->prec == CL_MIXED ? sizeof(float) : sizeof(double);
     std::vector<char> raw((size_t)lat->V * 72 * rs);

@@ -14,6 +14,7 @@ struct Launch {
     const BatchHdr* hdr;
     const RunArgs* runs;
     int blocks[NKIND];
+    int nrun;
     hipStream_t stream;
 };
 
@@ -27,6 +28,7 @@ hipError_t launch_update(const Launch& L, int prec);
 hipError_t launch_cool(const Launch& L, int prec, int parity, int iter);
 hipError_t launch_gradnorm(const Launch& L, int prec, int iter);
 hipError_t launch_measure(const Launch& L, int prec);
+hipError_t launch_finalize(const Launch& L, int what, int iter);
 hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st);
 hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st);
 
@@ -37,6 +39,7 @@ inline void blocks_per_kind(int V, int out[NKIND])
     out[KIND_SITE] = (V + kBlock - 1) / kBlock;
     out[KIND_COOL] = (2 * V + kBlock - 1) / kBlock;
     out[KIND_PLANE] = (6 * V + kBlock - 1) / kBlock;
+    out[KIND_DRIFT] = (4 * V + kBlock / 2 - 1) / (kBlock / 2);
 }
 
 constexpr int kNumPartials = 7;  // the most partial values any kernel publishes

@@ -4,10 +4,11 @@
 // with coalesced complex-element SoA loads (see lattice.hpp).
 //
 // Every kernel walks logical blocks of a batch of runs (a single lattice is a
-// batch of one) and reduces per-run scalars deterministically: each logical
-// block writes its partial, the last block of the run to arrive (atomic
-// counter) sums the partials in a fixed order and updates the run's control
-// block, so no host round trip sits between the kernels of a step.
+// batch of one).  Per-run scalars (max drift, unitarity norm, observables) are
+// reduced deterministically: each logical block stores its partial and a
+// one-block-per-run finalize kernel sums them in a fixed order and updates the
+// run's control block on the device, so no host round trip sits between the
+// kernels of a step and no grid-wide fence is needed inside a sweep.
 #include "engine.hpp"
 
 #include <math.h>
@@ -53,27 +54,15 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double* lds /* NV*
     __syncthreads();
 }
 
-// Publish this logical block's partials and report whether it is the last
-// block of its run to do so.  Thread 0 holds v[] (from block_reduce).
+// Store this logical block's partials (thread 0 holds v[] from block_reduce).
 template <int NV>
-__device__ __forceinline__ bool publish_partials(const RunArgs& ra, int kind, int lb, const double (&v)[NV],
-                                                 uint32_t* cnt)
+__device__ __forceinline__ void store_partials(const RunArgs& ra, int kind, int lb, const double (&v)[NV])
 {
-    __shared__ int s_last;
-    const int nblk = ra.nblk[kind];
     if (threadIdx.x == 0) {
+        const int nblk = ra.nblk[kind];
 #pragma unroll
-        for (int j = 0; j < NV; ++j)
-            __hip_atomic_store(&ra.part[j * nblk + lb], v[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t prev = atomicAdd(cnt, 1u);
-        s_last = (prev == (uint32_t)(nblk - 1));
-        if (s_last) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < NV; ++j) ra.part[j * nblk + lb] = v[j];
     }
-    __syncthreads();
-    const bool last = s_last != 0;
-    if (last) __threadfence();
-    return last;
 }
 
 // Fixed-order sum (or max) of one partial array of the run; valid in thread 0.
@@ -81,9 +70,9 @@ template <bool MAX = false>
 __device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, int j, double* lds)
 {
     const int nblk = ra.nblk[kind];
-    double acc = MAX ? 0.0 : 0.0;
+    double acc = 0.0;
     for (int i = threadIdx.x; i < nblk; i += kBlock) {
-        const double p = __hip_atomic_load(&ra.part[j * nblk + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double p = ra.part[j * nblk + i];
         acc = MAX ? (isnan(p) || isnan(acc) ? NAN : fmax(acc, p)) : acc + p;
     }
     double v[1] = {acc};
@@ -170,21 +159,7 @@ __global__ void __launch_bounds__(kBlock) k_init(const BatchHdr* __restrict__ hd
     }
     double v[1] = {un};
     block_reduce<1>(v, lds);
-    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_UPDATE])) {
-        const double tot = gather_partials(ra, KIND_LINK, 0, lds);
-        if (threadIdx.x == 0) {
-            Ctrl* c = ra.ctrl;
-            c->unorm = tot;
-            c->step = 0;
-            c->bound = 0.0;
-            c->eps = 0.0;
-            c->kmax = 0.0;
-            c->d_pre = tot / (12.0 * ra.V) - 1.0;
-            c->status = ST_OK;
-            c->hist_n = 0;
-            c->alpha_cur = 0.0;
-        }
-    }
+    store_partials(ra, KIND_LINK, lb, v);
     CLGC_END_BLOCKS
 }
 
@@ -198,13 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_unorm(const BatchHdr* __restrict__ h
     if (tid < 4 * ra.V) un = (double)m_norm2(load_mat((const cx<T>*)ra.U, tid, 4 * ra.V));
     double v[1] = {un};
     block_reduce<1>(v, lds);
-    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_UPDATE])) {
-        const double tot = gather_partials(ra, KIND_LINK, 0, lds);
-        if (threadIdx.x == 0) {
-            ra.ctrl->unorm = tot;
-            ra.ctrl->status = isfinite(tot) ? ra.ctrl->status : (int)ST_NONFINITE;
-        }
-    }
+    store_partials(ra, KIND_LINK, lb, v);
     CLGC_END_BLOCKS
 }
 
@@ -299,109 +268,125 @@ __global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ 
 //   I = X1 e1e2e3 + e1 X2 e2e3 + e1e2 X3 e3 + e1e2e3 X0     (Horner, 8 products),
 //   J = X0 e3'e2'e1' + e3' X3 e2'e1' + e3'e2' X2 e1' + e3'e2'e1' X1   (8 products),
 // X_k the dual clover matrix of the loop's plane at d_k, sigma = s sign(nu - mu).
-// The two accumulators Lacc = cb A + ct sigma I and Racc = cb A' - ct sigma J
-// give Khat = TL(e0 Lacc - Racc e0').
+// A logical block owns 128 links: waves 0-1 accumulate the forward chains
+// Lacc = sum (cb A + ct sigma I) and form e0 Lacc, waves 2-3 the backward
+// chains Racc = sum (cb A' - ct sigma J) and form Racc e0'; the backward half
+// hands its matrix over through LDS and the forward half stores
+// Khat = TL(e0 Lacc - Racc e0').  Splitting by chain (not by lane) keeps every
+// wave on one code path and halves the live matrices per lane.
+
+constexpr int kDriftLinks = kBlock / 2;
 
 template <typename T, bool THETA>
 __global__ void __launch_bounds__(kBlock) k_drift(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
 {
     __shared__ double lds[8];
-    CLGC_FOR_BLOCKS(KIND_LINK)
-    double kn2 = 0.0;
-    if (tid < 4 * ra.V) {
+    __shared__ cx<T> xch[9][kDriftLinks];
+    CLGC_FOR_BLOCKS(KIND_DRIFT)
+    const int l = lb * kDriftLinks + (int)(threadIdx.x & (kDriftLinks - 1));
+    const int back = threadIdx.x >= kDriftLinks;  // wave-uniform
+    const bool ok = l < 4 * ra.V;
+    mat3<T> M;
+    if (ok) {
         int mu, p, h;
-        link_decompose(ra, tid, mu, p, h);
+        link_decompose(ra, l, mu, p, h);
         const Site x = site_coords(ra, p, h);
         const Site d1 = site_move(ra, x, mu, +1);
         const cx<T> cb = {T(0), T(ra.beta / 3.0)};
         const double tn = 1.0 / (128.0 * M_PI * M_PI);
         const cx<T> ct = {T(ra.th_re * tn), T(ra.th_im * tn)};
         const cx<T>* __restrict__ Fb = (const cx<T>*)ra.F;
-        mat3<T> Lacc = m_zero<T>(), Racc = m_zero<T>();
+        const int fs = 6 * ra.V;
+        mat3<T> acc = m_zero<T>();
 #pragma unroll 1
         for (int nn = 0; nn < 3; ++nn) {
             const int nu = nn + (nn >= mu);
             const int P = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
-            const int Pd = dual_plane(P);
-            const int fo = Pd * ra.V;
+            const int fo = dual_plane(P) * ra.V;
 #pragma unroll 1
             for (int si = 0; si < 2; ++si) {
                 const int s = si ? -1 : 1;
                 const Site d3 = site_move(ra, x, nu, s);
                 const Site d2 = site_move(ra, d1, nu, s);
-                // raw links of the loop and which of them enter inverted
-                const mat3<T> l1 = ldU<T>(ra, nu, s > 0 ? d1 : d2);
-                const mat3<T> l2 = ldU<T>(ra, mu, d3);
-                const mat3<T> l3 = ldU<T>(ra, nu, s > 0 ? x : d3);
-                const mat3<T> l1a = m_adj(l1), l2a = m_adj(l2), l3a = m_adj(l3);
-                const mat3<T>& e1 = s > 0 ? l1 : l1a;
-                const mat3<T>& e1i = s > 0 ? l1a : l1;
-                const mat3<T>& e2 = l2a;
-                const mat3<T>& e2i = l2;
-                const mat3<T>& e3 = s > 0 ? l3a : l3;
-                const mat3<T>& e3i = s > 0 ? l3 : l3a;
-                if (!THETA) {
-                    const mat3<T> A = e1 * (e2 * e3);
-                    m_axpy(Lacc, cb, A);
-                    m_axpy(Racc, cb, m_adj(A));
-                } else {
-                    const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(P));
-                    const cx<T> cts = {sig * ct.re, sig * ct.im};
-                    const cx<T> mcts = {-cts.re, -cts.im};
-                    const mat3<T> X0 = load_mat(Fb, fo + p * ra.Vh + h, 6 * ra.V);
-                    const mat3<T> X1 = load_mat(Fb, fo + link_off(ra, 0, d1), 6 * ra.V);
-                    const mat3<T> X2 = load_mat(Fb, fo + link_off(ra, 0, d2), 6 * ra.V);
-                    const mat3<T> X3 = load_mat(Fb, fo + link_off(ra, 0, d3), 6 * ra.V);
-                    // forward chain
-                    mat3<T> I = X3 * e3;
-                    m_mac(I, e3, X0);
+                // raw links of the loop: e1 = l1 (s>0) or l1^-1, e2 = l2^-1, e3 = l3^-1 (s>0) or l3
+                const int o1 = link_off(ra, nu, s > 0 ? d1 : d2);
+                const int o2 = link_off(ra, mu, d3);
+                const int o3 = link_off(ra, nu, s > 0 ? x : d3);
+                const cx<T>* __restrict__ Ub = (const cx<T>*)ra.U;
+                const int us = 4 * ra.V;
+                const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(P));
+                const cx<T> cts = {sig * ct.re, sig * ct.im};
+                if (!back) {
+                    // forward chain from d1 to d0
+                    mat3<T> e3 = load_mat(Ub, o3, us);
+                    if (s > 0) e3 = m_adj(e3);
+                    const mat3<T> e2 = m_adj(load_mat(Ub, o2, us));
                     mat3<T> Pm = e2 * e3;
-                    mat3<T> I2 = X2 * Pm;
-                    m_mac(I2, e2, I);
-                    Pm = e1 * Pm;
-                    I = X1 * Pm;
-                    m_mac(I, e1, I2);
-                    m_axpy(Lacc, cb, Pm);
-                    m_axpy(Lacc, cts, I);
-                    // backward chain
-                    mat3<T> J = X2 * e1i;
-                    m_mac(J, e1i, X1);
+                    if (!THETA) {
+                        mat3<T> e1 = load_mat(Ub, o1, us);
+                        if (s < 0) e1 = m_adj(e1);
+                        m_axpy(acc, cb, e1 * Pm);
+                    } else {
+                        mat3<T> I = load_mat(Fb, fo + link_off(ra, 0, d3), fs) * e3;
+                        m_mac(I, e3, load_mat(Fb, fo + p * ra.Vh + h, fs));
+                        mat3<T> I2 = load_mat(Fb, fo + link_off(ra, 0, d2), fs) * Pm;
+                        m_mac(I2, e2, I);
+                        mat3<T> e1 = load_mat(Ub, o1, us);
+                        if (s < 0) e1 = m_adj(e1);
+                        Pm = e1 * Pm;
+                        I = load_mat(Fb, fo + link_off(ra, 0, d1), fs) * Pm;
+                        m_mac(I, e1, I2);
+                        m_axpy(acc, cb, Pm);
+                        m_axpy(acc, cts, I);
+                    }
+                } else {
+                    // backward chain from d0 to d1 (inverse links)
+                    mat3<T> e1i = load_mat(Ub, o1, us);
+                    if (s > 0) e1i = m_adj(e1i);
+                    const mat3<T> e2i = load_mat(Ub, o2, us);
                     mat3<T> Rm = e2i * e1i;
-                    mat3<T> J2 = X3 * Rm;
-                    m_mac(J2, e2i, J);
-                    Rm = e3i * Rm;
-                    J = X0 * Rm;
-                    m_mac(J, e3i, J2);
-                    m_axpy(Racc, cb, Rm);
-                    m_axpy(Racc, mcts, J);
+                    if (!THETA) {
+                        mat3<T> e3i = load_mat(Ub, o3, us);
+                        if (s < 0) e3i = m_adj(e3i);
+                        m_axpy(acc, cb, e3i * Rm);
+                    } else {
+                        mat3<T> J = load_mat(Fb, fo + link_off(ra, 0, d2), fs) * e1i;
+                        m_mac(J, e1i, load_mat(Fb, fo + link_off(ra, 0, d1), fs));
+                        mat3<T> J2 = load_mat(Fb, fo + link_off(ra, 0, d3), fs) * Rm;
+                        m_mac(J2, e2i, J);
+                        mat3<T> e3i = load_mat(Ub, o3, us);
+                        if (s < 0) e3i = m_adj(e3i);
+                        Rm = e3i * Rm;
+                        J = load_mat(Fb, fo + p * ra.Vh + h, fs) * Rm;
+                        m_mac(J, e3i, J2);
+                        m_axpy(acc, cb, Rm);
+                        const cx<T> mcts = {-cts.re, -cts.im};
+                        m_axpy(acc, mcts, J);
+                    }
                 }
             }
         }
-        const mat3<T> e0 = ldU<T>(ra, mu, x);
-        mat3<T> M = e0 * Lacc;
-        M = M - Racc * m_adj(e0);
+        const mat3<T> e0 = load_mat((const cx<T>*)ra.U, l, 4 * ra.V);
+        M = back ? acc * m_adj(e0) : e0 * acc;
+    }
+    const int slot = threadIdx.x & (kDriftLinks - 1);
+    if (back && ok) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) xch[e][slot] = M.e[e / 3][e % 3];
+    }
+    __syncthreads();
+    double kn2 = 0.0;
+    if (!back && ok) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) M.e[e / 3][e % 3] = M.e[e / 3][e % 3] - xch[e][slot];
         const mat3<T> K = m_traceless(M);
-        store_mat((cx<T>*)ra.K, tid, 4 * ra.V, K);
+        store_mat((cx<T>*)ra.K, l, 4 * ra.V, K);
         kn2 = 0.5 * (double)m_norm2(K);
         if (!isfinite(kn2)) kn2 = INFINITY;
     }
     double v[1] = {kn2};
     block_reduce<1, true>(v, lds);
-    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_DRIFT])) {
-        const double km2 = gather_partials<true>(ra, KIND_LINK, 0, lds);
-        if (threadIdx.x == 0) {
-            Ctrl* c = ra.ctrl;
-            const double kmax = sqrt(km2);
-            double eps = ra.eps0;
-            if (ra.adaptive) {
-                if (c->bound <= 0.0) c->bound = ra.drift_bound > 0.0 ? ra.drift_bound : ra.eps0 * kmax;
-                if (kmax > 0.0 && c->bound / kmax < ra.eps0) eps = c->bound / kmax;
-            }
-            c->kmax = kmax;
-            c->eps = eps;
-            if (!isfinite(kmax)) c->status = ST_NONFINITE;
-        }
-    }
+    store_partials(ra, KIND_DRIFT, lb, v);
     CLGC_END_BLOCKS
 }
 
@@ -470,16 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const BatchHdr* __restrict__ 
     }
     double v[1] = {un};
     block_reduce<1>(v, lds);
-    if (publish_partials(ra, KIND_LINK, lb, v, &ra.ctrl->cnt[CNT_UPDATE])) {
-        const double tot = gather_partials(ra, KIND_LINK, 0, lds);
-        if (threadIdx.x == 0 && ok) {
-            Ctrl* c = ra.ctrl;
-            c->unorm = tot;
-            c->d_pre = tot / (12.0 * ra.V) - 1.0;
-            c->step = step + 1;
-            if (!isfinite(tot)) c->status = ST_NONFINITE;
-        }
-    }
+    store_partials(ra, KIND_LINK, lb, v);
     CLGC_END_BLOCKS
 }
 
@@ -636,14 +612,7 @@ __global__ void __launch_bounds__(kBlock) k_cool(const BatchHdr* __restrict__ hd
             // the unitarity norm of the cooled configuration
             double v[1] = {un};
             block_reduce<1>(v, lds);
-            if (publish_partials(ra, KIND_COOL, lb, v, &cr->cnt[CNT_COOL])) {
-                const double tot = gather_partials(ra, KIND_COOL, 0, lds);
-                if (threadIdx.x == 0) {
-                    cr->unorm = tot;
-                    if (iter + 1 <= kMaxCoolHist) cr->hist_un[iter + 1] = tot;
-                    if (!isfinite(tot)) cr->status = ST_NONFINITE;
-                }
-            }
+            store_partials(ra, KIND_COOL, lb, v);
         }
     }
     CLGC_END_BLOCKS
@@ -678,14 +647,7 @@ __global__ void __launch_bounds__(kBlock) k_gradnorm(const BatchHdr* __restrict_
         }
         double v[1] = {fs};
         block_reduce<1>(v, lds);
-        if (publish_partials(ra, KIND_SITE, lb, v, &cr->cnt[CNT_GRAD])) {
-            const double tot = gather_partials(ra, KIND_SITE, 0, lds);
-            if (threadIdx.x == 0) {
-                const double D = tot / (8.0 * ra.V);
-                cr->alpha_cur = ra.alpha / D;
-                if (!(D > 0.0) || !isfinite(cr->alpha_cur)) cr->status = ST_NONFINITE;
-            }
-        }
+        store_partials(ra, KIND_SITE, lb, v);
     }
     CLGC_END_BLOCKS
 }
@@ -737,13 +699,103 @@ __global__ void __launch_bounds__(kBlock) k_measure(const BatchHdr* __restrict__
         v[5] = q.im;
     }
     block_reduce<7>(v, lds);
-    if (publish_partials(ra, KIND_SITE, lb, v, &ra.ctrl->cnt[CNT_MEASURE])) {
-        for (int j = 0; j < 7; ++j) {
-            const double tot = gather_partials(ra, KIND_SITE, j, lds);
-            if (threadIdx.x == 0) ra.ctrl->obs[j] = tot;
+    store_partials(ra, KIND_SITE, lb, v);
+    CLGC_END_BLOCKS
+}
+
+// ---------------------------------------------------------------------------
+// finalize: one block per run sums (or maxes) the partials of the kernel that
+// just ran, in a fixed order, and updates the run's control block.
+
+__global__ void __launch_bounds__(kBlock) k_finalize(const BatchHdr* __restrict__ hdr,
+                                                     const RunArgs* __restrict__ runs, int what, int iter)
+{
+    __shared__ double lds[8];
+    for (int r = blockIdx.x; r < hdr->nrun; r += gridDim.x) {
+        const RunArgs& ra = runs[r];
+        Ctrl* c = ra.ctrl;
+        const bool ok = c->status == ST_OK;
+        switch (what) {
+        case FIN_INIT: {
+            const double tot = gather_partials(ra, KIND_LINK, 0, lds);
+            if (threadIdx.x == 0) {
+                c->unorm = tot;
+                c->step = 0;
+                c->bound = 0.0;
+                c->eps = 0.0;
+                c->kmax = 0.0;
+                c->d_pre = tot / (12.0 * ra.V) - 1.0;
+                c->status = isfinite(tot) ? ST_OK : ST_NONFINITE;
+                c->hist_n = 0;
+                c->alpha_cur = 0.0;
+            }
+            break;
+        }
+        case FIN_UNORM: {
+            const double tot = gather_partials(ra, KIND_LINK, 0, lds);
+            if (threadIdx.x == 0) {
+                c->unorm = tot;
+                if (!isfinite(tot)) c->status = ST_NONFINITE;
+            }
+            break;
+        }
+        case FIN_DRIFT: {
+            const double km2 = gather_partials<true>(ra, KIND_DRIFT, 0, lds);
+            if (threadIdx.x == 0) {
+                const double kmax = sqrt(km2);
+                double eps = ra.eps0;
+                if (ra.adaptive) {
+                    if (c->bound <= 0.0) c->bound = ra.drift_bound > 0.0 ? ra.drift_bound : ra.eps0 * kmax;
+                    if (kmax > 0.0 && c->bound / kmax < ra.eps0) eps = c->bound / kmax;
+                }
+                c->kmax = kmax;
+                c->eps = eps;
+                if (!isfinite(kmax)) c->status = ST_NONFINITE;
+            }
+            break;
+        }
+        case FIN_UPDATE: {
+            if (!ok) break;  // the update kernel left the links untouched
+            const double tot = gather_partials(ra, KIND_LINK, 0, lds);
+            if (threadIdx.x == 0) {
+                c->unorm = tot;
+                c->d_pre = tot / (12.0 * ra.V) - 1.0;
+                c->step = c->step + 1;
+                if (!isfinite(tot)) c->status = ST_NONFINITE;
+            }
+            break;
+        }
+        case FIN_COOL: {
+            if (!ok || iter >= ra.n_cool) break;
+            const double tot = gather_partials(ra, KIND_COOL, 0, lds);
+            if (threadIdx.x == 0) {
+                c->unorm = tot;
+                if (iter + 1 <= kMaxCoolHist) c->hist_un[iter + 1] = tot;
+                if (!isfinite(tot)) c->status = ST_NONFINITE;
+            }
+            break;
+        }
+        case FIN_GRAD: {
+            if (!ok || ra.mode != 2 || iter >= ra.n_cool) break;
+            const double tot = gather_partials(ra, KIND_SITE, 0, lds);
+            if (threadIdx.x == 0) {
+                const double D = tot / (8.0 * ra.V);
+                c->alpha_cur = ra.alpha / D;
+                if (!(D > 0.0) || !isfinite(c->alpha_cur)) c->status = ST_NONFINITE;
+            }
+            break;
+        }
+        case FIN_MEASURE: {
+            for (int j = 0; j < 7; ++j) {
+                const double tot = gather_partials(ra, KIND_SITE, j, lds);
+                if (threadIdx.x == 0) c->obs[j] = tot;
+            }
+            break;
+        }
+        default:
+            break;
         }
     }
-    CLGC_END_BLOCKS
 }
 
 // ---------------------------------------------------------------------------
@@ -813,11 +865,11 @@ hipError_t launch_clover(const Launch& L, int prec)
 hipError_t launch_drift(const Launch& L, int prec, bool theta)
 {
     if (prec) {
-        if (theta) CLGC_LAUNCH((k_drift<float, true>), KIND_LINK);
-        else CLGC_LAUNCH((k_drift<float, false>), KIND_LINK);
+        if (theta) CLGC_LAUNCH((k_drift<float, true>), KIND_DRIFT);
+        else CLGC_LAUNCH((k_drift<float, false>), KIND_DRIFT);
     } else {
-        if (theta) CLGC_LAUNCH((k_drift<double, true>), KIND_LINK);
-        else CLGC_LAUNCH((k_drift<double, false>), KIND_LINK);
+        if (theta) CLGC_LAUNCH((k_drift<double, true>), KIND_DRIFT);
+        else CLGC_LAUNCH((k_drift<double, false>), KIND_DRIFT);
     }
     return hipGetLastError();
 }
@@ -852,6 +904,13 @@ hipError_t launch_measure(const Launch& L, int prec)
 {
     if (prec) CLGC_LAUNCH(k_measure<float>, KIND_SITE);
     else CLGC_LAUNCH(k_measure<double>, KIND_SITE);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Launch& L, int what, int iter)
+{
+    const int g = L.nrun > 0 ? L.nrun : 1;
+    hipLaunchKernelGGL(k_finalize, dim3(g), dim3(kBlock), 0, L.stream, L.hdr, L.runs, what, iter);
     return hipGetLastError();
 }
 

@@ -32,11 +32,13 @@ enum Kind : int {
     KIND_SITE = 1,   // one site: measurement                  (V threads)
     KIND_COOL = 2,   // one (site of one parity, mu): cooling  (2V threads)
     KIND_PLANE = 3,  // one (site, plane): clover field        (6V threads)
-    NKIND = 4
+    KIND_DRIFT = 4,  // one chain (forward/backward) of a link: drift (8V threads)
+    NKIND = 5
 };
 
-// reduction counters (one per reducing kernel)
-enum Counter : int { CNT_DRIFT = 0, CNT_UPDATE = 1, CNT_COOL = 2, CNT_MEASURE = 3, CNT_GRAD = 4, NCNT = 8 };
+// what a finalize launch reduces
+enum Finalize : int { FIN_INIT = 0, FIN_UNORM = 1, FIN_DRIFT = 2, FIN_UPDATE = 3, FIN_COOL = 4, FIN_GRAD = 5,
+                      FIN_MEASURE = 6 };
 
 enum Status : int { ST_OK = 0, ST_NONFINITE = 1 };
 
@@ -49,13 +51,12 @@ struct Ctrl {
     double unorm;       // sum Tr U U^dagger of the current links
     double alpha_cur;   // alpha_ad of the cooling step in progress
     double d_pre;       // distance after the last CL update
-    double obs[6];      // plaquette re/im, Q re/im, UN, (spare)
+    double obs[8];      // sums: Tr P re/im, Tr P^-1 re/im, clover Q bracket re/im, UN
     double hist_un[kMaxCoolHist + 1];
     double hist_alpha[kMaxCoolHist];
     int64_t step;       // CL step counter n (Philox counter word 1)
     int32_t status;     // Status
     int32_t hist_n;     // cooling steps recorded
-    uint32_t cnt[NCNT]; // last-block-done counters
 };
 
 // Per-run descriptor (device copy written by the host when it changes).

@@ -1,0 +1,274 @@
+"""GPU tests beyond single-operation parity: graph replay vs eager launches,
+the mixed-precision path's tolerances, the 16^4 production size, larger
+lattices on sampled links, error and runaway handling, determinism and
+checkpoint/resume.  All calls go through the C ABI."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from tests import latutil as lu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1311_1056_amd as cl
+    return cl
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_graph_replay_matches_eager(cl):
+    """cl_run_steps replays a captured step graph; it must give exactly what
+    individual launches give, replay after replay."""
+    dims = (4, 4, 4, 8)
+    a = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=9)
+    b = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=9)
+    a.init(True)
+    b.init(True)
+    for rep in range(3):
+        a.run_steps(2, 1e-2, True, 3, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+        ma = a.measure()  # eager work and a synchronisation between replays
+        for _ in range(2):
+            b.langevin_step(1e-2, adaptive=True, sync=False)
+            b.gauge_cool(3, 1e-2, 1.0, cl.CL_ALPHA_UNORM, sync=False)
+        mb = b.measure()
+        assert np.array_equal(a.get_links(), b.get_links()), rep
+        assert ma == mb
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("theta", [0.0, 1.0])
+def test_mixed_precision_step_tolerance(cl, orc, theta):
+    """Mixed path (FP32 links, drift, cooling; FP64 det renormalisation,
+    reductions and control) against the FP64 oracle from the same links and
+    noise: link error <= 1e-5 relative, observables within 1e-6."""
+    dims = (8, 8, 8, 8)
+    U = orc.init_links(dims, 4, 0.3, 0.05)
+    lat = cl.Lattice(dims, 6.0, theta, cl.CL_MIXED, seed=4)
+    lat.set_links(U)
+    Uin = lat.get_links()  # the FP32-rounded input both sides start from
+    W = Uin.copy()
+    bound = 0.0
+    worst = 0.0
+    for n in range(2):
+        eps = lat.langevin_step(1e-2, adaptive=True)
+        e_ref, _, bound = orc.langevin_step(dims, W, 6.0, theta, 4, n, 1e-2, True, bound=bound)
+        assert abs(eps - e_ref) <= 1e-5 * e_ref
+        lat.gauge_cool(10, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+        orc.gauge_cool(dims, W, 10, 1e-2, 1.0, 1)
+        got = lat.get_links()
+        err = relerr(got, W)
+        worst = max(worst, err)
+        assert err <= 1e-5
+        o = lat.measure()
+        assert abs(o["plaq"] - orc.plaquette(dims, W)) <= 1e-6
+        q = orc.topological_charge(dims, W)
+        assert abs(o["q"] - q) <= 1e-6 * max(1, abs(q))
+        assert abs(o["d"] - orc.distance(dims, W)) <= 1e-6
+        lat.set_links(W)  # restart the next step from identical (rounded) links
+        W = lat.get_links()
+    say(f"mixed theta={theta}: worst per-step link error {worst:.2e}")
+    lat.close()
+
+
+def test_mixed_drift_tolerance(cl, orc):
+    dims = (4, 4, 4, 4)
+    rng = np.random.default_rng(7)
+    U = lu.random_links(rng, dims, 0.5, 0.2)
+    lat = cl.Lattice(dims, 6.0, 1.0, cl.CL_MIXED)
+    lat.set_links(U)
+    Ur = lat.get_links()
+    K = lat.compute_drift()
+    assert relerr(K, orc.drift(dims, Ur, 6.0, 1.0)) < 1e-5
+    lat.close()
+
+
+@pytest.mark.slow
+def test_production_size_16x4_full_step(cl, orc):
+    """The benchmark's workload and launch configuration: 16^4, beta 6, theta 1,
+    adaptive eps, 10 D_1 cooling steps; one full step compared link by link."""
+    dims = (16, 16, 16, 16)
+    lat = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=3)
+    lat.init(True, 0.3, 0.05)
+    U0 = lat.get_links()
+    lat.run_steps(1, 1e-2, True, 10, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    got = lat.get_links()
+    o = lat.measure()
+    W = U0.copy()
+    obs, bound = orc.run(dims, W, 6.0, 1.0, 3, 1, 1e-2, True, 10, 1e-2, 1.0, 1)
+    err = relerr(got, W)
+    say(f"16^4 full step: link rel err {err:.2e}")
+    assert err < 1e-12
+    assert abs(o["plaq"] - complex(obs[0, 2], obs[0, 3])) < 1e-12
+    assert abs(o["q"] - complex(obs[0, 4], obs[0, 5])) < 1e-11
+    assert abs(o["d"] - obs[0, 1]) < 1e-13
+    assert abs(o["eps"] - obs[0, 6]) < 1e-14
+    lat.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(24, 24, 24, 24), (32, 32, 32, 32)])
+def test_large_lattice_sampled_drift(cl, orc, dims):
+    """24^4 and 32^4 (mixed, and FP64 at 24^4): the drift of sampled links against
+    the oracle, which evaluates each sampled link on its own."""
+    rng = np.random.default_rng(8)
+    V = lu.volume(dims)
+    sel = np.sort(rng.choice(4 * V, size=48, replace=False))
+    sel = np.concatenate([sel, [0, 4 * V - 1]])
+    precs = [cl.CL_MIXED] + ([cl.CL_FP64] if dims[0] == 24 else [])
+    for prec in precs:
+        lat = cl.Lattice(dims, 6.0, 1.0, prec, seed=4)
+        lat.init(True, 0.3, 0.05)
+        U = lat.get_links()
+        K = lat.compute_drift().reshape(-1, 18)[sel]
+        ref = orc.drift_links(dims, U, 6.0, 1.0, sel)
+        tol = 1e-12 if prec == cl.CL_FP64 else 1e-5
+        err = relerr(K, ref)
+        say(f"{dims} prec={prec}: sampled drift rel err {err:.2e}")
+        assert err < tol
+        lat.close()
+
+
+def test_minimum_and_ragged_lattices(cl, orc):
+    """2^4 (every neighbour wraps) and extents with a ragged last block."""
+    for dims in [(2, 2, 2, 2), (2, 6, 4, 10), (6, 2, 2, 2)]:
+        lat = cl.Lattice(dims, 5.5, 0.8, cl.CL_FP64, seed=2)
+        lat.init(True)
+        U = lat.get_links()
+        lat.langevin_step(5e-3)
+        lat.gauge_cool(3, 5e-3, 1.0, cl.CL_ALPHA_GRAD)
+        W = U.copy()
+        orc.langevin_step(dims, W, 5.5, 0.8, 2, 0, 5e-3)
+        orc.gauge_cool(dims, W, 3, 5e-3, 1.0, 2)
+        assert relerr(lat.get_links(), W) < 1e-12, dims
+        lat.close()
+
+
+def test_errors(cl):
+    with pytest.raises(cl.ClError) as e:
+        cl.Lattice((3, 4, 4, 4), 6.0)
+    assert e.value.status == cl.CL_EINVAL
+    import torch
+    desc = cl.make_desc((4, 4, 4, 4), 6.0)
+    need = cl.cl_lattice_bytes(desc)
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    h = ctypes.c_void_p()
+    st = cl.lib.cl_lattice_create(ctypes.byref(desc), ctypes.c_void_p(buf.data_ptr()), need - 256, None,
+                                  ctypes.byref(h))
+    assert st == cl.CL_ENOMEM
+    lat = cl.Lattice((4, 4, 4, 4), 6.0)
+    with pytest.raises(cl.ClError) as e:
+        lat.set_links(np.zeros(10))
+    assert e.value.status == cl.CL_EINVAL
+    with pytest.raises(cl.ClError):
+        lat.langevin_step(-1.0)
+    with pytest.raises(cl.ClError):
+        lat.gauge_cool(100, 1e-2)
+    lat.close()
+
+
+def test_runaway_is_detected_and_not_advanced(cl, orc):
+    """A non-finite link makes the drift non-finite: the step reports
+    CL_ENONFINITE and leaves the links as they were."""
+    dims = (4, 4, 4, 4)
+    U = orc.init_links(dims, 1)
+    U[17, 2, 4] = np.nan
+    lat = cl.Lattice(dims, 6.0, 1.0)
+    lat.set_links(U)
+    with pytest.raises(cl.ClError) as e:
+        lat.langevin_step(1e-2, adaptive=True)
+    assert e.value.status == cl.CL_ENONFINITE
+    got = lat.get_links()
+    assert np.array_equal(np.isnan(got), np.isnan(U))
+    assert np.array_equal(got[~np.isnan(U)], U[~np.isnan(U)])
+    # a healthy lattice next to it is unaffected
+    ok = cl.Lattice(dims, 6.0, 1.0)
+    ok.init(True)
+    assert ok.langevin_step(1e-2) == 1e-2
+    ok.close()
+    lat.close()
+
+
+def test_determinism_and_resume(cl):
+    dims = (4, 4, 8, 4)
+    kw = dict(eps0=1e-2, adaptive=True, n_cool=4, eps_c=1e-2, alpha=1.0, mode=cl.CL_ALPHA_UNORM)
+    a = cl.Lattice(dims, 6.0, 0.5, cl.CL_FP64, seed=21)
+    b = cl.Lattice(dims, 6.0, 0.5, cl.CL_FP64, seed=21)
+    a.init(True)
+    b.init(True)
+    a.run_steps(4, **kw)
+    b.run_steps(2, **kw)
+    step, bound = b.get_state()
+    links = b.get_links()
+    b.close()
+    assert step == 2 and bound > 0
+    c = cl.Lattice(dims, 6.0, 0.5, cl.CL_FP64, seed=21)
+    c.set_links(links)
+    c.set_state(step, bound)
+    c.run_steps(2, **kw)
+    assert np.array_equal(a.get_links(), c.get_links())
+    d = cl.Lattice(dims, 6.0, 0.5, cl.CL_FP64, seed=21)
+    d.init(True)
+    d.run_steps(4, **kw)
+    assert np.array_equal(a.get_links(), d.get_links())
+    for x in (a, c, d):
+        x.close()
+
+
+def test_config2_shape_trajectory(cl, orc):
+    """8^4, beta 6, seed 2, adaptive eps (eps0 1e-2), 10 adaptive-alpha cooling
+    steps: per-step eps, distances and plaquette over a short trajectory."""
+    dims = (8, 8, 8, 8)
+    lat = cl.Lattice(dims, 6.0, 0.0, cl.CL_FP64, seed=2)
+    lat.init(True)
+    W = orc.init_links(dims, 2)
+    obs, _ = orc.run(dims, W, 6.0, 0.0, 2, 4, 1e-2, True, 10, 1e-2, 1.0, 1)
+    for n in range(4):
+        lat.run_steps(1, 1e-2, True, 10, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+        o = lat.measure()
+        assert abs(o["eps"] - obs[n, 6]) < 1e-12 * obs[n, 6]
+        assert abs(o["d_pre"] - obs[n, 0]) < 1e-12
+        assert abs(o["d"] - obs[n, 1]) < 1e-12
+        assert abs(o["plaq"] - complex(obs[n, 2], obs[n, 3])) < 1e-12
+    assert relerr(lat.get_links(), W) < 1e-11
+    lat.close()
+
+
+def test_real_langevin_and_cooling_invariants(cl):
+    """theta = 0 from an SU(3) start keeps links unitary (cooling is then a
+    no-op); on a complex configuration cooling lowers the norm monotonically
+    and leaves the plaquette and Q unchanged."""
+    dims = (4, 4, 4, 4)
+    rng = np.random.default_rng(3)
+    S = lu.from_c(lu.random_su3(rng, n=lu.volume(dims) * 4)).reshape(-1, 4, 18)
+    lat = cl.Lattice(dims, 6.0, 0.0)
+    lat.set_links(S)
+    for _ in range(5):
+        lat.langevin_step(1e-2)
+    assert abs(lat.unitarity_norm()) < 1e-13
+    lat.close()
+    U = lu.random_links(rng, dims, 0.5, 0.3)
+    lat = cl.Lattice(dims, 6.0, 1.0)
+    lat.set_links(U)
+    o0 = lat.measure()
+    lat.gauge_cool(20, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    o1 = lat.measure()
+    hu, _ = lat.cool_history()
+    assert np.all(np.diff(hu) <= 0)
+    assert abs(o1["plaq"] - o0["plaq"]) < 1e-13
+    assert abs(o1["q"] - o0["q"]) < 1e-12
+    assert o1["d"] < o0["d"]
+    lat.close()

@@ -280,3 +280,15 @@ def test_run_resume_is_bitwise(orc):
     np.testing.assert_array_equal(a, b)
     np.testing.assert_array_equal(oa, np.concatenate([ob1, ob2]))
     assert np.all(oa[:, 1] <= oa[:, 0])  # cooling lowers d
+
+
+def test_sampled_drift_equals_full_drift(orc):
+    """The per-link entry point (clover matrices evaluated on demand) gives the
+    same drift as the whole-lattice one."""
+    rng = np.random.default_rng(22)
+    dims = (4, 2, 4, 2)
+    U = lu.random_links(rng, dims)
+    for theta in (0.0, 0.7 + 0.2j):
+        K = orc.drift(dims, U, 5.0, theta).reshape(-1, 18)
+        sel = np.arange(0, 4 * lu.volume(dims), 3)
+        np.testing.assert_array_equal(orc.drift_links(dims, U, 5.0, theta, sel), K[sel])

@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--served-runs", type=int, default=256, help="runs in the served mix (0: skip)")
+    ap.add_argument("--served-budget-mb", type=int, default=2048)
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -188,6 +190,64 @@ def cpu_baseline(args):
                       f"same {'x'.join(map(str, dims))} workload, FP64, {threads} OpenMP threads, {dt:.1f} s"}
 
 
+SERVED_SHAPES = [(6, 6, 6, 6), (8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (8, 8, 8, 16), (24, 24, 24, 8)]
+
+
+def served_mix(n, seed=6):
+    """The served request mix: lattice uniform over six shapes, beta ~ U[5.7, 6.2],
+    theta ~ U[0, 2], 50..500 steps, 1..20 cooling steps per update, eps0 ~ U[1e-3, 1e-2],
+    FP64 or mixed with probability 1/2; run seed 1000 + index."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    runs = []
+    for i in range(n):
+        runs.append(dict(dims=SERVED_SHAPES[int(rng.integers(6))], beta=float(rng.uniform(5.7, 6.2)),
+                         theta=float(rng.uniform(0.0, 2.0)), n_steps=int(rng.integers(50, 501)),
+                         n_cool=int(rng.integers(1, 21)), eps0=float(rng.uniform(1e-3, 1e-2)),
+                         prec=int(rng.integers(2)), seed=1000 + i))
+    return runs
+
+
+def served(args, capacity_lus):
+    """Continuous batching of the request mix arriving as a Poisson stream at
+    0.7x the single-run FP64 capacity, under an HBM budget small enough that
+    admission queues."""
+    import numpy as np
+    import paper_1311_1056_amd as cl
+    runs = served_mix(args.served_runs)
+    work = np.array([4 * np.prod(r["dims"]) * r["n_steps"] for r in runs], dtype=float)
+    rate = 0.7 * capacity_lus / work.mean()  # runs per second
+    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / rate, len(runs)))
+    srv = cl.Server(args.served_budget_mb << 20)
+    results = []
+    i = 0
+    t0 = time.perf_counter()
+    while len(results) < len(runs):
+        now = time.perf_counter() - t0
+        while i < len(runs) and arrivals[i] <= now:
+            r = runs[i]
+            srv.submit(r["dims"], r["beta"], r["theta"], r["prec"], r["seed"], r["n_steps"], r["eps0"], True,
+                       r["n_cool"], r["eps0"], 1.0, cl.CL_ALPHA_UNORM, tag=i)
+            i += 1
+        a, p = srv.step()
+        results += srv.poll()
+        if a == 0 and p == 0 and i < len(runs):
+            time.sleep(max(0.0, min(arrivals[i] - (time.perf_counter() - t0), 0.01)))
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lu = sum(r["link_updates"] for r in results)
+    bad = sum(1 for r in results if r["status"] != 0)
+    return {"value": round(lu / makespan, 1), "unit": "link-updates/s", "runs": len(runs), "failed_runs": bad,
+            "step_ms_p50": round(st["step_ms_p50"], 3), "step_ms_p99": round(st["step_ms_p99"], 3),
+            "queue_wait_s_p50": round(st["wait_s_p50"], 3), "queue_wait_s_p99": round(st["wait_s_p99"], 3),
+            "makespan_s": round(makespan, 2), "gpu_busy_s": round(st["busy_s"], 2),
+            "batch_steps": st["batch_steps"], "arrival_rate_runs_per_s": round(rate, 3),
+            "budget_bytes": args.served_budget_mb << 20,
+            "mix": "6^4, 8^4, 12^4, 16^4, 8^3x16, 24^3x8; beta U[5.7,6.2]; theta U[0,2]; 50-500 steps; "
+                   "1-20 D1 cooling steps; eps0 U[1e-3,1e-2]; FP64 or mixed; Poisson arrivals at 0.7x capacity"}
+
+
 def copy_calibration(mib):
     import torch
     n = mib * 1024 * 1024 // 4
@@ -241,6 +301,8 @@ def main():
         out["mixed"] = {"value": round(mx["value"], 1), "ms_per_step": round(mx["ms_per_step"], 4),
                         "dtype": "f32 links/drift/cooling, f64 det renorm, reductions and control",
                         "roofline": mrf}
+    if args.served_runs > 0 and args.precision == "fp64":
+        out["served"] = served(args, res["value"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

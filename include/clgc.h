@@ -170,6 +170,63 @@ cl_status cl_timing_enable(cl_lattice* lat, int enable);
  * since cl_timing_enable(lat, 1). */
 cl_status cl_timing_read(cl_lattice* lat, double* total_ms, int64_t* launches, int cap);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent CL runs on one GPU.
+ *
+ * A server owns a caller-provided device arena.  Submitted runs wait in a
+ * FIFO queue until their device footprint (cl_lattice_bytes) fits in the
+ * arena; admitted runs are initialised and then advance together: every
+ * cl_server_step performs one CL update plus that run's own number of
+ * cooling steps for every active run, with one launch per kernel kind over
+ * the concatenated logical blocks of all runs of a precision (replayed from a
+ * captured graph).  Finished runs are measured, retired and their memory
+ * reused by the next admissions.  A run's arithmetic does not depend on what
+ * it is batched with.
+ * ------------------------------------------------------------------------- */
+typedef struct cl_server cl_server;
+
+typedef struct {
+    cl_lattice_desc lattice;   /* extents, beta, theta, precision, seed */
+    cl_step_desc step;         /* eps0, adaptive, drift bound */
+    cl_cool_desc cool;         /* cooling steps per update (0..64), eps_c, alpha, mode */
+    int32_t n_steps;           /* CL steps to run (>= 1) */
+    double sigma_x, sigma_y;   /* perturbed start as in cl_lattice_init */
+    uint64_t tag;              /* caller's label, returned with the result */
+} cl_run_desc;
+
+typedef struct {
+    uint64_t run_id, tag;
+    int32_t status;            /* CL_OK, or CL_ENONFINITE for a run retired on a runaway */
+    int32_t steps_done;
+    cl_obs obs;                /* measured after the last step */
+    double t_submit, t_admit, t_finish;  /* seconds on the server's clock */
+    double step_ms_p50, step_ms_p99;     /* wall time of the batch steps the run advanced in */
+    int64_t link_updates;      /* 4 V x steps_done */
+} cl_run_result;
+
+typedef struct {
+    int32_t pending, active, finished;
+    size_t bytes_in_use, bytes_budget;
+    int64_t batch_steps, link_updates;
+    double busy_s;                       /* summed wall time of batch steps */
+    double step_ms_p50, step_ms_p99;     /* over all (run, step) samples */
+    double wait_s_p50, wait_s_p99;       /* queue wait (admit - submit) of finished runs */
+} cl_server_stats;
+
+/* arena: device memory owned by the caller (256-byte aligned) holding the
+ * server's tables and every admitted run; its size is the HBM budget. */
+cl_status cl_server_create(void* arena, size_t arena_bytes, void* hip_stream, cl_server** out);
+/* Queue a run (non-blocking).  CL_EBUDGET if it can never fit the arena. */
+cl_status cl_server_submit(cl_server* srv, const cl_run_desc* run, uint64_t* run_id);
+/* Admit what fits, advance every active run by one step, retire finished
+ * runs.  Waits for the GPU at the end of the step.  n_active / n_pending may
+ * be NULL. */
+cl_status cl_server_step(cl_server* srv, int* n_active, int* n_pending);
+/* Move up to cap finished results into out (oldest first). */
+cl_status cl_server_poll(cl_server* srv, cl_run_result* out, int cap, int* n_done);
+cl_status cl_server_stats_get(cl_server* srv, cl_server_stats* out);
+cl_status cl_server_destroy(cl_server* srv);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* cl_last_error(void);
 

@@ -47,6 +47,27 @@ class cl_obs(ctypes.Structure):
                 ("step", ctypes.c_int64)]
 
 
+class cl_run_desc(ctypes.Structure):
+    _fields_ = [("lattice", cl_lattice_desc), ("step", cl_step_desc), ("cool", cl_cool_desc),
+                ("n_steps", ctypes.c_int32), ("sigma_x", ctypes.c_double), ("sigma_y", ctypes.c_double),
+                ("tag", ctypes.c_uint64)]
+
+
+class cl_run_result(ctypes.Structure):
+    _fields_ = [("run_id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("steps_done", ctypes.c_int32), ("obs", cl_obs), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_finish", ctypes.c_double), ("step_ms_p50", ctypes.c_double),
+                ("step_ms_p99", ctypes.c_double), ("link_updates", ctypes.c_int64)]
+
+
+class cl_server_stats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int32), ("active", ctypes.c_int32), ("finished", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_size_t), ("bytes_budget", ctypes.c_size_t),
+                ("batch_steps", ctypes.c_int64), ("link_updates", ctypes.c_int64), ("busy_s", ctypes.c_double),
+                ("step_ms_p50", ctypes.c_double), ("step_ms_p99", ctypes.c_double),
+                ("wait_s_p50", ctypes.c_double), ("wait_s_p99", ctypes.c_double)]
+
+
 class ClError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"clgc error {status}: {msg}")
@@ -77,6 +98,12 @@ def _load():
         "cl_cool_history": [vp, dp, dp, ctypes.c_int, P(ctypes.c_int)],
         "cl_run_steps": [vp, P(cl_step_desc), P(cl_cool_desc), ctypes.c_int],
         "cl_timing_enable": [vp, ctypes.c_int],
+        "cl_server_create": [vp, sz, vp, P(vp)],
+        "cl_server_submit": [vp, P(cl_run_desc), P(ctypes.c_uint64)],
+        "cl_server_step": [vp, P(ctypes.c_int), P(ctypes.c_int)],
+        "cl_server_poll": [vp, P(cl_run_result), ctypes.c_int, P(ctypes.c_int)],
+        "cl_server_stats_get": [vp, P(cl_server_stats)],
+        "cl_server_destroy": [vp],
         "cl_timing_read": [vp, dp, P(ctypes.c_int64), ctypes.c_int],
     }
     for name, args in sigs.items():
@@ -235,3 +262,69 @@ class Lattice:
         cnt = (ctypes.c_int64 * n)()
         _check(lib.cl_timing_read(self.handle, _dp(ms), cnt, n))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS) if cnt[i]}
+
+
+def _obs_dict(o):
+    return {"plaq": complex(o.plaq[0], o.plaq[1]), "q": complex(o.q[0], o.q[1]),
+            "action": complex(o.action[0], o.action[1]), "d": o.unorm_d, "d_pre": o.d_pre,
+            "eps": o.eps, "kmax": o.kmax, "alpha": o.alpha, "bound": o.bound, "step": o.step}
+
+
+class Server:
+    """Continuous batching of independent CL runs inside one device arena of
+    `budget_bytes` (the HBM budget runs are admitted against)."""
+
+    def __init__(self, budget_bytes, device="cuda:0", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.arena = torch.empty(int(budget_bytes) + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.arena.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p()
+        _check(lib.cl_server_create(ctypes.c_void_p(ptr), int(budget_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, dims, beta, theta=0.0, precision=CL_FP64, seed=0, n_steps=1, eps0=1e-2, adaptive=True,
+               n_cool=10, eps_c=None, alpha=1.0, mode=CL_ALPHA_UNORM, sigma_x=0.3, sigma_y=0.05, tag=0,
+               drift_bound=0.0):
+        d = cl_run_desc(make_desc(dims, beta, theta, precision, seed),
+                        cl_step_desc(float(eps0), int(adaptive), float(drift_bound)),
+                        cl_cool_desc(int(n_cool), float(eps0 if eps_c is None else eps_c), float(alpha), int(mode)),
+                        int(n_steps), float(sigma_x), float(sigma_y), int(tag))
+        rid = ctypes.c_uint64()
+        _check(lib.cl_server_submit(self.handle, ctypes.byref(d), ctypes.byref(rid)))
+        return rid.value
+
+    def step(self):
+        a, p = ctypes.c_int(), ctypes.c_int()
+        _check(lib.cl_server_step(self.handle, ctypes.byref(a), ctypes.byref(p)))
+        return a.value, p.value
+
+    def poll(self, cap=256):
+        buf = (cl_run_result * cap)()
+        n = ctypes.c_int()
+        _check(lib.cl_server_poll(self.handle, buf, cap, ctypes.byref(n)))
+        out = []
+        for r in buf[:n.value]:
+            out.append({"run_id": r.run_id, "tag": r.tag, "status": r.status, "steps_done": r.steps_done,
+                        "obs": _obs_dict(r.obs), "t_submit": r.t_submit, "t_admit": r.t_admit,
+                        "t_finish": r.t_finish, "step_ms_p50": r.step_ms_p50, "step_ms_p99": r.step_ms_p99,
+                        "link_updates": r.link_updates})
+        return out
+
+    def stats(self):
+        st = cl_server_stats()
+        _check(lib.cl_server_stats_get(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in cl_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib.cl_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,14 +18,16 @@
 
 #include "../../include/clgc.h"
 #include "engine.hpp"
+#include "host.hpp"
 
 using namespace clgc;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-cl_status fail(cl_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace clgc {
+
 cl_status fail(cl_status st, const char* fmt, ...)
 {
     char buf[512];
@@ -36,18 +38,6 @@ cl_status fail(cl_status st, const char* fmt, ...)
     g_err = buf;
     return st;
 }
-
-#define HIP_TRY(expr)                                                                           \
-    do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
-        if (e_ != hipSuccess) return fail(CL_EHIP, "%s: %s", #expr, hipGetErrorString(e_));      \
-    } while (0)
-
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Layout {
-    size_t U, K, F, part, ctrl, args, hdr, total;
-};
 
 Layout layout_of(const cl_lattice_desc& d)
 {
@@ -93,36 +83,7 @@ cl_status check_desc(const cl_lattice_desc* d)
     return CL_OK;
 }
 
-}  // namespace
-
-struct cl_lattice {
-    cl_lattice_desc desc;
-    int prec;
-    int V;
-    char* base;
-    size_t bytes;
-    hipStream_t stream;
-    Layout lay;
-    RunArgs args;      // host mirror of the device RunArgs
-    RunArgs* d_args;
-    BatchHdr* d_hdr;
-    Ctrl* d_ctrl;
-    Launch L;
-    bool F_valid;      // clover field matches the current links
-    bool has_theta;
-    // benchmark instrumentation (cl_timing_enable)
-    bool timing;
-    struct Mark {
-        int kind;
-        hipEvent_t a, b;
-    };
-    std::vector<Mark> marks;
-    std::vector<hipEvent_t> pool;
-    // one captured CL step (update + cooling), replayed by cl_run_steps
-    hipStream_t cap_stream;
-    hipGraphExec_t step_graph;
-    int graph_key[3];   // n_cool, mode, has_theta of the captured step
-};
+}  // namespace clgc
 
 namespace {
 
@@ -240,7 +201,7 @@ void soa_to_host(const cl_lattice* lat, const void* raw, double* host)
 cl_status enqueue_step(cl_lattice* lat)
 {
     const bool theta = lat->has_theta;
-    if (theta && !lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec));
+    if (theta && !lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
     TIMED(lat, CL_K_DRIFT, launch_drift(lat->L, lat->prec, theta));
     TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_DRIFT, 0));
     TIMED(lat, CL_K_UPDATE, launch_update(lat->L, lat->prec));
@@ -539,7 +500,7 @@ cl_status cl_unitarity_norm(cl_lattice* lat, double* d)
 cl_status cl_measure(cl_lattice* lat, cl_obs* out)
 {
     if (!lat || !out) return fail(CL_EINVAL, "NULL argument");
-    if (!lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec));
+    if (!lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
     lat->F_valid = true;
     TIMED(lat, CL_K_MEASURE, launch_measure(lat->L, lat->prec));
     TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_MEASURE, 0));
@@ -580,7 +541,7 @@ cl_status cl_compute_drift(cl_lattice* lat, double* host_K, size_t n_doubles)
     Ctrl saved;
     cl_status st = read_ctrl(lat, &saved);
     if (st) return st;
-    if (lat->has_theta && !lat->F_valid) HIP_TRY(launch_clover(lat->L, lat->prec));
+    if (lat->has_theta && !lat->F_valid) HIP_TRY(launch_clover(lat->L, lat->prec, 0));
     lat->F_valid = lat->has_theta;
     HIP_TRY(launch_drift(lat->L, lat->prec, lat->has_theta));
     HIP_TRY(launch_finalize(lat->L, FIN_DRIFT, 0));

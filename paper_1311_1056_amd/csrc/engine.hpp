@@ -9,6 +9,14 @@
 
 namespace clgc {
 
+// compact per-run state copied to the host after a batched step
+struct GatherRec {
+    int64_t step;
+    int32_t status;
+    int32_t pad;
+    double eps, kmax, unorm, d_pre;
+};
+
 // one launch of a batch: device header and run table, logical blocks per kind
 struct Launch {
     const BatchHdr* hdr;
@@ -22,13 +30,14 @@ hipError_t launch_init(const Launch& L, int prec, int perturbed, double sx, doub
 hipError_t launch_unorm(const Launch& L, int prec);
 hipError_t launch_unpack(const Launch& L, int prec, const double* aos);
 hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos);
-hipError_t launch_clover(const Launch& L, int prec);
+hipError_t launch_clover(const Launch& L, int prec, int only_theta);
 hipError_t launch_drift(const Launch& L, int prec, bool theta);
 hipError_t launch_update(const Launch& L, int prec);
 hipError_t launch_cool(const Launch& L, int prec, int parity, int iter);
 hipError_t launch_gradnorm(const Launch& L, int prec, int iter);
 hipError_t launch_measure(const Launch& L, int prec);
 hipError_t launch_finalize(const Launch& L, int what, int iter);
+hipError_t launch_gather(const Launch& L, GatherRec* out);
 hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st);
 hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st);
 

@@ -1,0 +1,64 @@
+// host.hpp -- host-side internals shared by the C ABI (api.cpp) and the
+// run server (server.cpp): error reporting, the device-buffer layout of a
+// lattice and the lattice handle itself.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <vector>
+
+#include "../../include/clgc.h"
+#include "engine.hpp"
+
+namespace clgc {
+
+// sets the thread-local message returned by cl_last_error and returns st
+cl_status fail(cl_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return ::clgc::fail(CL_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// byte offsets of a lattice's pieces inside its device buffer
+struct Layout {
+    size_t U, K, F, part, ctrl, args, hdr, total;
+};
+
+Layout layout_of(const cl_lattice_desc& d);
+cl_status check_desc(const cl_lattice_desc* d);
+
+}  // namespace clgc
+
+struct cl_lattice {
+    cl_lattice_desc desc;
+    int prec;
+    int V;
+    char* base;
+    size_t bytes;
+    hipStream_t stream;
+    clgc::Layout lay;
+    clgc::RunArgs args;      // host mirror of the device RunArgs
+    clgc::RunArgs* d_args;
+    clgc::BatchHdr* d_hdr;
+    clgc::Ctrl* d_ctrl;
+    clgc::Launch L;
+    bool F_valid;      // clover field matches the current links
+    bool has_theta;
+    // benchmark instrumentation (cl_timing_enable)
+    bool timing;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
+    // one captured CL step (update + cooling), replayed by cl_run_steps
+    hipStream_t cap_stream;
+    hipGraphExec_t step_graph;
+    int graph_key[3];   // n_cool, mode, has_theta of the captured step
+};

@@ -221,10 +221,12 @@ __global__ void __launch_bounds__(kBlock) k_pack(const BatchHdr* __restrict__ hd
 // x in the (mu, nu) plane of (L - L^{-1})
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+__global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+                                                   int only_theta)
 {
     CLGC_FOR_BLOCKS(KIND_PLANE)
-    if (tid < 6 * ra.V) {
+    // in a batched step only the runs with a theta term need the field
+    if (tid < 6 * ra.V && !(only_theta && !ra.has_theta)) {
         const int P = tid / ra.V;
         const int rem = tid - P * ra.V;
         const int p = rem >= ra.Vh;
@@ -316,13 +318,15 @@ __global__ void __launch_bounds__(kBlock) k_drift(const BatchHdr* __restrict__ h
                 const int us = 4 * ra.V;
                 const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(P));
                 const cx<T> cts = {sig * ct.re, sig * ct.im};
+                // block-uniform: a batch can mix runs with and without a theta term
+                const bool th = THETA && ra.has_theta;
                 if (!back) {
                     // forward chain from d1 to d0
                     mat3<T> e3 = load_mat(Ub, o3, us);
                     if (s > 0) e3 = m_adj(e3);
                     const mat3<T> e2 = m_adj(load_mat(Ub, o2, us));
                     mat3<T> Pm = e2 * e3;
-                    if (!THETA) {
+                    if (!th) {
                         mat3<T> e1 = load_mat(Ub, o1, us);
                         if (s < 0) e1 = m_adj(e1);
                         m_axpy(acc, cb, e1 * Pm);
@@ -345,7 +349,7 @@ __global__ void __launch_bounds__(kBlock) k_drift(const BatchHdr* __restrict__ h
                     if (s > 0) e1i = m_adj(e1i);
                     const mat3<T> e2i = load_mat(Ub, o2, us);
                     mat3<T> Rm = e2i * e1i;
-                    if (!THETA) {
+                    if (!th) {
                         mat3<T> e3i = load_mat(Ub, o3, us);
                         if (s < 0) e3i = m_adj(e3i);
                         m_axpy(acc, cb, e3i * Rm);
@@ -798,6 +802,23 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const BatchHdr* __restrict_
     }
 }
 
+// compact per-run status for the host after a batched step
+__global__ void k_gather(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs, GatherRec* out)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < hdr->nrun; r += gridDim.x * blockDim.x) {
+        const Ctrl* c = runs[r].ctrl;
+        GatherRec g;
+        g.step = c->step;
+        g.status = c->status;
+        g.pad = 0;
+        g.eps = c->eps;
+        g.kmax = c->kmax;
+        g.unorm = c->unorm;
+        g.d_pre = c->d_pre;
+        out[r] = g;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // small control kernels (stream-ordered writes of host-side parameters)
 
@@ -855,10 +876,10 @@ hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos
     return hipGetLastError();
 }
 
-hipError_t launch_clover(const Launch& L, int prec)
+hipError_t launch_clover(const Launch& L, int prec, int only_theta)
 {
-    if (prec) CLGC_LAUNCH(k_clover<float>, KIND_PLANE);
-    else CLGC_LAUNCH(k_clover<double>, KIND_PLANE);
+    if (prec) CLGC_LAUNCH(k_clover<float>, KIND_PLANE, only_theta);
+    else CLGC_LAUNCH(k_clover<double>, KIND_PLANE, only_theta);
     return hipGetLastError();
 }
 
@@ -911,6 +932,12 @@ hipError_t launch_finalize(const Launch& L, int what, int iter)
 {
     const int g = L.nrun > 0 ? L.nrun : 1;
     hipLaunchKernelGGL(k_finalize, dim3(g), dim3(kBlock), 0, L.stream, L.hdr, L.runs, what, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Launch& L, GatherRec* out)
+{
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(kBlock), 0, L.stream, L.hdr, L.runs, out);
     return hipGetLastError();
 }
 

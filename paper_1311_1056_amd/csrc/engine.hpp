@@ -47,8 +47,9 @@ inline void blocks_per_kind(int V, int out[NKIND])
     out[KIND_LINK] = (4 * V + kBlock - 1) / kBlock;
     out[KIND_SITE] = (V + kBlock - 1) / kBlock;
     out[KIND_COOL] = (2 * V + kBlock - 1) / kBlock;
-    out[KIND_PLANE] = (6 * V + kBlock - 1) / kBlock;
-    out[KIND_DRIFT] = (4 * V + kBlock / 2 - 1) / (kBlock / 2);
+    const int Vh = V / 2;
+    out[KIND_PLANE] = 12 * ((Vh + kBlock - 1) / kBlock);            // (region, plane, parity)
+    out[KIND_DRIFT] = 8 * ((Vh + kBlock / 2 - 1) / (kBlock / 2));   // (region, mu, parity)
 }
 
 constexpr int kNumPartials = 7;  // the most partial values any kernel publishes

@@ -83,8 +83,19 @@ __device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, i
 // ---------------------------------------------------------------------------
 // logical-block iteration
 
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup w runs
+// on XCD w mod 8), and each XCD has its own L2.  Logical blocks are therefore
+// dealt out so that XCD x works through the contiguous range
+// [x Q, (x+1) Q) of the logical-block space: neighbouring sites, whose links
+// and clover matrices a block re-reads, stay in one L2.  Grids are launched as
+// a multiple of eight (or grid-stride with a multiple-of-eight stride), so the
+// XCD of a logical slot never changes.
 #define CLGC_FOR_BLOCKS(KIND)                                                  \
-    for (int gb_ = blockIdx.x; gb_ < hdr->total[KIND]; gb_ += gridDim.x) {     \
+    const int total_ = hdr->total[KIND];                                       \
+    const int q_ = (total_ + kXcds - 1) / kXcds;                               \
+    for (int gb0_ = blockIdx.x; gb0_ < kXcds * q_; gb0_ += gridDim.x) {        \
+        const int gb_ = (gb0_ % kXcds) * q_ + gb0_ / kXcds;                    \
+        if (gb_ >= total_) continue;                                           \
         const int run_ = find_run(hdr, KIND, gb_);                             \
         const RunArgs& ra = runs[run_];                                        \
         const int lb = gb_ - hdr->begin[KIND][run_];                           \
@@ -225,12 +236,12 @@ __global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ 
                                                    int only_theta)
 {
     CLGC_FOR_BLOCKS(KIND_PLANE)
+    // logical block -> (region of 256 half-indices, plane, parity), regions major
+    const int P = (lb % 12) >> 1, p = lb & 1;
+    const int h = (lb / 12) * kBlock + (int)threadIdx.x;
     // in a batched step only the runs with a theta term need the field
-    if (tid < 6 * ra.V && !(only_theta && !ra.has_theta)) {
-        const int P = tid / ra.V;
-        const int rem = tid - P * ra.V;
-        const int p = rem >= ra.Vh;
-        const int h = rem - p * ra.Vh;
+    if (h < ra.Vh && !(only_theta && !ra.has_theta)) {
+        const int tid_f = P * ra.V + p * ra.Vh + h;
         const int mu = P < 3 ? 0 : (P < 5 ? 1 : 2);
         const int nu = P < 3 ? P + 1 : (P < 5 ? P - 1 : 3);
         const Site x = site_coords(ra, p, h);
@@ -254,7 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ 
         // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
         L = m_adj(Unxmn) * ((ldU<T>(ra, mu, xmn) * ldU<T>(ra, nu, xmnpm)) * m_adj(Umx));
         F = F + (L - m_adj(L));
-        store_mat((cx<T>*)ra.F, tid, 6 * ra.V, F);
+        store_mat((cx<T>*)ra.F, tid_f, 6 * ra.V, F);
     }
     CLGC_END_BLOCKS
 }
@@ -285,13 +296,16 @@ __global__ void __launch_bounds__(kBlock) k_drift(const BatchHdr* __restrict__ h
     __shared__ double lds[8];
     __shared__ cx<T> xch[9][kDriftLinks];
     CLGC_FOR_BLOCKS(KIND_DRIFT)
-    const int l = lb * kDriftLinks + (int)(threadIdx.x & (kDriftLinks - 1));
+    // logical block -> (region of 128 half-indices, direction, parity): the eight
+    // (mu, parity) blocks of a region are adjacent, so one XCD covers all the
+    // links of a contiguous slab of sites
+    const int mu = (lb & 7) >> 1, p = lb & 1;
+    const int h = (lb >> 3) * kDriftLinks + (int)(threadIdx.x & (kDriftLinks - 1));
+    const int l = (mu * 2 + p) * ra.Vh + h;
     const int back = threadIdx.x >= kDriftLinks;  // wave-uniform
-    const bool ok = l < 4 * ra.V;
+    const bool ok = h < ra.Vh;
     mat3<T> M;
     if (ok) {
-        int mu, p, h;
-        link_decompose(ra, l, mu, p, h);
         const Site x = site_coords(ra, p, h);
         const Site d1 = site_move(ra, x, mu, +1);
         const cx<T> cb = {T(0), T(ra.beta / 3.0)};
@@ -840,7 +854,12 @@ __global__ void k_write_state(Ctrl* c, int64_t step, double bound)
 
 namespace {
 
-inline int grid_of(const Launch& L, int kind) { return L.blocks[kind] > 0 ? L.blocks[kind] : 1; }
+// a multiple of the XCD count, so that a logical slot keeps its XCD (see CLGC_FOR_BLOCKS)
+inline int grid_of(const Launch& L, int kind)
+{
+    const int b = L.blocks[kind] > 0 ? L.blocks[kind] : 1;
+    return (b + kXcds - 1) / kXcds * kXcds;
+}
 
 }  // namespace
 

@@ -23,6 +23,7 @@
 namespace clgc {
 
 constexpr int kBlock = 256;        // threads per logical block, all kernels
+constexpr int kXcds = 8;           // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kMaxRuns = 256;      // runs in one batched launch
 constexpr int kMaxCoolHist = 64;   // cooling steps per call kept in the history
 
@@ -90,9 +91,16 @@ struct BatchHdr {
 // ---------------------------------------------------------------------------
 // index arithmetic
 
+// lattice coordinates; four scalars (not an array) so that runtime direction
+// indices compile to selects and the struct stays in registers
 struct Site {
-    int x[4];
+    int x0, x1, x2, x3;
 };
+
+__device__ __forceinline__ int site_get(const Site& s, int mu)
+{
+    return mu == 0 ? s.x0 : (mu == 1 ? s.x1 : (mu == 2 ? s.x2 : s.x3));
+}
 
 __device__ __forceinline__ Site site_coords(const RunArgs& ra, int p, int h)
 {
@@ -100,36 +108,38 @@ __device__ __forceinline__ Site site_coords(const RunArgs& ra, int p, int h)
     int r = h / ra.Lh0;
     const int x0h = h - r * ra.Lh0;
     int q = r / ra.L[1];
-    s.x[1] = r - q * ra.L[1];
+    s.x1 = r - q * ra.L[1];
     r = q;
     q = r / ra.L[2];
-    s.x[2] = r - q * ra.L[2];
-    s.x[3] = q;
-    s.x[0] = 2 * x0h + ((p + s.x[1] + s.x[2] + s.x[3]) & 1);
+    s.x2 = r - q * ra.L[2];
+    s.x3 = q;
+    s.x0 = 2 * x0h + ((p + s.x1 + s.x2 + s.x3) & 1);
     return s;
 }
 
 __device__ __forceinline__ int site_half(const RunArgs& ra, const Site& s)
 {
-    return (s.x[0] >> 1) + ra.Lh0 * (s.x[1] + ra.L[1] * (s.x[2] + ra.L[2] * s.x[3]));
+    return (s.x0 >> 1) + ra.Lh0 * (s.x1 + ra.L[1] * (s.x2 + ra.L[2] * s.x3));
 }
 
-__device__ __forceinline__ int site_parity(const Site& s) { return (s.x[0] + s.x[1] + s.x[2] + s.x[3]) & 1; }
+__device__ __forceinline__ int site_parity(const Site& s) { return (s.x0 + s.x1 + s.x2 + s.x3) & 1; }
 
 __device__ __forceinline__ int site_lex(const RunArgs& ra, const Site& s)
 {
-    return s.x[0] + ra.L[0] * (s.x[1] + ra.L[1] * (s.x[2] + ra.L[2] * s.x[3]));
+    return s.x0 + ra.L[0] * (s.x1 + ra.L[1] * (s.x2 + ra.L[2] * s.x3));
 }
 
-// s + d * mu_hat with periodic wrap, |d| <= 2
-__device__ __forceinline__ Site site_move(const RunArgs& ra, Site s, int mu, int d)
+__device__ __forceinline__ int wrap(int v, int L) { return v >= L ? v - L : (v < 0 ? v + L : v); }
+
+// s + d * mu_hat with periodic wrap, d = +-1
+__device__ __forceinline__ Site site_move(const RunArgs& ra, const Site& s, int mu, int d)
 {
-    int v = s.x[mu] + d;
-    const int L = ra.L[mu];
-    v = v >= L ? v - L : v;
-    v = v < 0 ? v + L : v;
-    s.x[mu] = v;
-    return s;
+    Site r;
+    r.x0 = mu == 0 ? wrap(s.x0 + d, ra.L[0]) : s.x0;
+    r.x1 = mu == 1 ? wrap(s.x1 + d, ra.L[1]) : s.x1;
+    r.x2 = mu == 2 ? wrap(s.x2 + d, ra.L[2]) : s.x2;
+    r.x3 = mu == 3 ? wrap(s.x3 + d, ra.L[3]) : s.x3;
+    return r;
 }
 
 // offset (in complex elements, without the e * 4V term) of link (mu, site)

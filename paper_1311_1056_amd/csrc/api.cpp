@@ -76,7 +76,11 @@ cl_status check_desc(const cl_lattice_desc* d)
             return fail(CL_EINVAL, "extent L%d = %d must be even and >= 2", m, d->dims[m]);
         V *= d->dims[m];
     }
-    if (V * 4 * 9 > 2.0e9) return fail(CL_EINVAL, "lattice too large for 32-bit element indexing");
+    // the largest field (clover: 9 x 6V complex) must stay addressable by one
+    // 32-bit buffer resource
+    const double cbytes = d->precision == CL_MIXED ? 8.0 : 16.0;
+    if (9.0 * 6.0 * V * cbytes >= 4294967296.0)
+        return fail(CL_EINVAL, "lattice of %.0f sites too large (a field must stay below 4 GiB)", V);
     if (!(d->beta > 0)) return fail(CL_EINVAL, "beta must be > 0");
     if (!std::isfinite(d->theta_re) || !std::isfinite(d->theta_im)) return fail(CL_EINVAL, "theta not finite");
     if (d->precision != CL_FP64 && d->precision != CL_MIXED) return fail(CL_EINVAL, "unknown precision");

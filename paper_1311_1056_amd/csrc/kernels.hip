@@ -66,18 +66,28 @@ __device__ __forceinline__ void store_partials(const RunArgs& ra, int kind, int 
 }
 
 // Fixed-order sum (or max) of one partial array of the run; valid in thread 0.
+// Each thread issues eight independent loads before combining them, so the
+// gather costs a few memory round trips rather than one per loop trip.
 template <bool MAX = false>
 __device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, int j, double* lds)
 {
+    typedef __attribute__((address_space(1))) const double* gcd;
     const int nblk = ra.nblk[kind];
+    const gcd p = (gcd)(ra.part + (size_t)j * nblk);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kBlock) {
-        const double p = ra.part[j * nblk + i];
-        acc = MAX ? (isnan(p) || isnan(acc) ? NAN : fmax(acc, p)) : acc + p;
+    for (int base = 0; base < nblk; base += 8 * kBlock) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * kBlock + (int)threadIdx.x;
+            v[u] = i < nblk ? p[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = MAX ? (isnan(v[u]) || isnan(acc) ? NAN : fmax(acc, v[u])) : acc + v[u];
     }
-    double v[1] = {acc};
-    block_reduce<1, MAX>(v, lds);
-    return v[0];
+    double r[1] = {acc};
+    block_reduce<1, MAX>(r, lds);
+    return r[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -519,44 +529,95 @@ __device__ __forceinline__ void ch_exp_coeffs_real(T s, T t, T& f0, T& f1, T& f2
     f2 = z;
 }
 
-// E = exp(A), Ei = exp(-A) for Hermitian traceless A
+// square of a Hermitian matrix (Hermitian again)
 template <typename T>
-__device__ __forceinline__ void herm_exp_pair(const herm3<T>& A, mat3<T>& E, mat3<T>& Ei)
+__device__ __forceinline__ herm3<T> h_square(const herm3<T>& A)
 {
-    mat3<T> Af = h_full(A);
+    const T n01 = norm2(A.u01), n02 = norm2(A.u02), n12 = norm2(A.u12);
+    herm3<T> R;
+    R.d0 = A.d0 * A.d0 + n01 + n02;
+    R.d1 = n01 + A.d1 * A.d1 + n12;
+    R.d2 = n02 + n12 + A.d2 * A.d2;
+    R.u01 = cfma(A.u02, conj(A.u12), (A.d0 + A.d1) * A.u01);
+    R.u02 = cfma(A.u01, A.u12, (A.d0 + A.d2) * A.u02);
+    R.u12 = cfma(conj(A.u01), A.u02, (A.d1 + A.d2) * A.u12);
+    return R;
+}
+
+// c0 + c1 A + c2 A2 for Hermitian A, A2 and real coefficients
+template <typename T>
+__device__ __forceinline__ herm3<T> h_poly(T c0, T c1, T c2, const herm3<T>& A, const herm3<T>& A2)
+{
+    herm3<T> R;
+    R.d0 = fma(c2, A2.d0, fma(c1, A.d0, c0));
+    R.d1 = fma(c2, A2.d1, fma(c1, A.d1, c0));
+    R.d2 = fma(c2, A2.d2, fma(c1, A.d2, c0));
+    R.u01 = {fma(c2, A2.u01.re, c1 * A.u01.re), fma(c2, A2.u01.im, c1 * A.u01.im)};
+    R.u02 = {fma(c2, A2.u02.re, c1 * A.u02.re), fma(c2, A2.u02.im, c1 * A.u02.im)};
+    R.u12 = {fma(c2, A2.u12.re, c1 * A.u12.re), fma(c2, A2.u12.im, c1 * A.u12.im)};
+    return R;
+}
+
+// E = exp(A), Ei = exp(-A) for Hermitian traceless A, both kept Hermitian
+template <typename T>
+__device__ __forceinline__ void herm_exp_pair(herm3<T> A, herm3<T>& E, herm3<T>& Ei)
+{
     const T fro2 = A.d0 * A.d0 + A.d1 * A.d1 + A.d2 * A.d2 +
                    T(2) * (norm2(A.u01) + norm2(A.u02) + norm2(A.u12));
     int k = 0;
     if (fro2 > T(1)) {
         k = (int)ceil(T(0.5) * log2(fro2));
         const T sc = ldexp(T(1), -k);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Af.e[i][j] = sc * Af.e[i][j];
+        A.d0 *= sc;
+        A.d1 *= sc;
+        A.d2 *= sc;
+        A.u01 = sc * A.u01;
+        A.u02 = sc * A.u02;
+        A.u12 = sc * A.u12;
     }
-    const mat3<T> A2 = Af * Af;
-    const T s = T(0.5) * (A2.e[0][0].re + A2.e[1][1].re + A2.e[2][2].re);
-    const T t = m_det(Af).re;
+    const herm3<T> A2 = h_square(A);
+    const T s = T(0.5) * (A2.d0 + A2.d1 + A2.d2);
+    // det of a Hermitian matrix (real)
+    const cx<T> w = A.u01 * A.u12 * conj(A.u02);
+    const T t = A.d0 * A.d1 * A.d2 + T(2) * w.re - A.d0 * norm2(A.u12) - A.d1 * norm2(A.u02) -
+                A.d2 * norm2(A.u01);
     T f0, f1, f2, g0, g1, g2;
     ch_exp_coeffs_real(s, t, f0, f1, f2);
     ch_exp_coeffs_real(s, -t, g0, g1, g2);
+    E = h_poly(f0, f1, f2, A, A2);
+    Ei = h_poly(g0, -g1, g2, A, A2);
+    for (int i = 0; i < k; ++i) {
+        E = h_square(E);
+        Ei = h_square(Ei);
+    }
+}
+
+// H U for Hermitian H
+template <typename T>
+__device__ __forceinline__ mat3<T> h_mul(const herm3<T>& H, const mat3<T>& U)
+{
+    mat3<T> r;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            E.e[i][j] = {fma(f1, Af.e[i][j].re, f2 * A2.e[i][j].re), fma(f1, Af.e[i][j].im, f2 * A2.e[i][j].im)};
-            Ei.e[i][j] = {fma(-g1, Af.e[i][j].re, g2 * A2.e[i][j].re), fma(-g1, Af.e[i][j].im, g2 * A2.e[i][j].im)};
-        }
+    for (int j = 0; j < 3; ++j) {
+        r.e[0][j] = cfma(H.u02, U.e[2][j], cfma(H.u01, U.e[1][j], H.d0 * U.e[0][j]));
+        r.e[1][j] = cfma(H.u12, U.e[2][j], cfma(conj(H.u01), U.e[0][j], H.d1 * U.e[1][j]));
+        r.e[2][j] = cfma(conj(H.u12), U.e[1][j], cfma(conj(H.u02), U.e[0][j], H.d2 * U.e[2][j]));
+    }
+    return r;
+}
+
+// U H for Hermitian H
+template <typename T>
+__device__ __forceinline__ mat3<T> mul_h(const mat3<T>& U, const herm3<T>& H)
+{
+    mat3<T> r;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        E.e[i][i].re += f0;
-        Ei.e[i][i].re += g0;
+        r.e[i][0] = cfma(U.e[i][2], conj(H.u02), cfma(U.e[i][1], conj(H.u01), H.d0 * U.e[i][0]));
+        r.e[i][1] = cfma(U.e[i][2], conj(H.u12), cfma(U.e[i][0], H.u01, H.d1 * U.e[i][1]));
+        r.e[i][2] = cfma(U.e[i][1], H.u12, cfma(U.e[i][0], H.u02, H.d2 * U.e[i][2]));
     }
-    for (int i = 0; i < k; ++i) {
-        E = E * E;
-        Ei = Ei * Ei;
-    }
+    return r;
 }
 
 template <typename T, int PAR>
@@ -616,10 +677,10 @@ __global__ void __launch_bounds__(kBlock) k_cool(const BatchHdr* __restrict__ hd
             A.u01 = coef * G.u01;
             A.u02 = coef * G.u02;
             A.u12 = coef * G.u12;
-            mat3<T> E, Ei;
+            herm3<T> E, Ei;
             herm_exp_pair(A, E, Ei);
-            const mat3<T> Nf = E * Uf;
-            const mat3<T> Nb = Ub * Ei;
+            const mat3<T> Nf = h_mul(E, Uf);
+            const mat3<T> Nb = mul_h(Ub, Ei);
             cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
             store_mat(Uw, of, 4 * ra.V, Nf);
             store_mat(Uw, ob, 4 * ra.V, Nb);

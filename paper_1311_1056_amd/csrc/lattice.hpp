@@ -148,20 +148,80 @@ __device__ __forceinline__ int link_off(const RunArgs& ra, int mu, const Site& s
     return (mu * 2 + site_parity(s)) * ra.Vh + site_half(ra, s);
 }
 
+// Field access through raw buffer instructions.  The field pointers come
+// from the device-side run table, so plain pointer code compiles to flat
+// loads with a 64-bit address per element; a buffer resource instead keeps
+// the base in scalar registers, the element's offset (e * stride, uniform) in
+// the scalar offset and only the lane's 32-bit byte offset in a vector
+// register.  The resource's record count is the whole field (9 element
+// slabs of stride complex numbers; the hardware range check includes the
+// scalar offset): an offset beyond the field reads zero and drops the store
+// instead of touching memory outside it.  Fields are limited to 4 GiB.
+constexpr int kBufferWord3 = 0x00020000;  // gfx9-family raw buffer: 32-bit data format, no swizzle
+
 template <typename T>
-__device__ __forceinline__ mat3<T> load_mat(const cx<T>* __restrict__ base, int off, int stride)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const cx<T>* base, int stride)
 {
+    const uint32_t bytes = 9u * (uint32_t)stride * (uint32_t)sizeof(cx<T>);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, kBufferWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t lane_bytes, int elem_bytes)
+{
+    if constexpr (sizeof(T) == 8) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 v = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lane_bytes, elem_bytes, 0));
+        return {v.x, v.y};
+    } else {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const f2 v = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)lane_bytes, elem_bytes, 0));
+        return {v.x, v.y};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t rs, uint32_t lane_bytes, int elem_bytes, cx<T> c)
+{
+    if constexpr (sizeof(T) == 8) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        d2 v;
+        v.x = c.re;
+        v.y = c.im;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, (int)lane_bytes, elem_bytes, 0);
+    } else {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        f2 v;
+        v.x = c.re;
+        v.y = c.im;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, (int)lane_bytes, elem_bytes, 0);
+    }
+}
+
+// the matrix at lane offset off (complex units) of a field whose elements lie
+// stride complex numbers apart
+template <typename T>
+__device__ __forceinline__ mat3<T> load_mat(const cx<T>* base, int off, int stride)
+{
+    const __amdgpu_buffer_rsrc_t rs = field_rsrc(base, stride);
+    const uint32_t lane = (uint32_t)off * (uint32_t)sizeof(cx<T>);
+    const int es = stride * (int)sizeof(cx<T>);
     mat3<T> m;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) m.e[e / 3][e % 3] = base[e * stride + off];
+    for (int e = 0; e < 9; ++e) m.e[e / 3][e % 3] = buf_load<T>(rs, lane, e * es);
     return m;
 }
 
 template <typename T>
-__device__ __forceinline__ void store_mat(cx<T>* __restrict__ base, int off, int stride, const mat3<T>& m)
+__device__ __forceinline__ void store_mat(cx<T>* base, int off, int stride, const mat3<T>& m)
 {
+    const __amdgpu_buffer_rsrc_t rs = field_rsrc((const cx<T>*)base, stride);
+    const uint32_t lane = (uint32_t)off * (uint32_t)sizeof(cx<T>);
+    const int es = stride * (int)sizeof(cx<T>);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) base[e * stride + off] = m.e[e / 3][e % 3];
+    for (int e = 0; e < 9; ++e) buf_store<T>(rs, lane, e * es, m.e[e / 3][e % 3]);
 }
 
 // dual clover partner of plane P (0..5 = 01,02,03,12,13,23) and its sign:

@@ -62,18 +62,24 @@ def kernel_src_hash():
 
 
 def algorithmic_cost(kind, V, rs, theta):
-    """Algorithmic bytes and flops of one launch (roofline section).
+    """Algorithmic bytes and flops of one launch (kernels section).
 
-    Bytes: the compulsory HBM traffic (each field element read / written once).
-    Flops: 3x3 complex product = 108 FMA = 216 flops, adjugate = 9 x 2 complex
-    multiplies + 9 complex subtractions = 126 flops."""
+    Bytes: every field element the kernel must touch, read or written once.
+    Flops: 3x3 complex product = 108 FMA = 216 flops, adjugate = 126 flops,
+    Hermitian-times-general product = 162 flops, Hermitian exponential pair
+    (square, determinant, two 20-term real series, two polynomials) ~ 500."""
     L = 4 * V
     mat = 18 * rs
-    prod, adj = 216, 126
-    if kind in ("cool_even", "cool_odd"):
-        # every link read and written once; per site: G (8 Hermitian products of 54 flops),
-        # two Hermitian exponentials (~2 x 400), 8 link products
-        return {"bytes": L * 2 * mat, "flops": (V // 2) * (8 * 54 + 800 + 8 * prod)}
+    prod, adj, hprod, hexp = 216, 126, 162, 500
+    if kind == "cool_omega":
+        # read every link once, write Omega and Omega^-1 (18 reals) per even site;
+        # per even site: 8 U U^dagger-type Hermitian products (54 flops) + one pair
+        return {"bytes": L * mat + (V // 2) * 18 * rs, "flops": (V // 2) * (8 * 54 + hexp)}
+    if kind == "cool_apply":
+        # read and write every link once, read Omega pairs; per link: even transform,
+        # odd transform (Hermitian products), per odd site: G and one exponential pair
+        return {"bytes": L * 2 * mat + (V // 2) * 18 * rs,
+                "flops": L * 2 * hprod + (V // 2) * (8 * 54 + hexp)}
     if kind == "drift":
         wil = 6 * (2 * prod + adj) + 2 * prod + adj
         top = 6 * (14 * prod + 2 * adj) if theta else 0
@@ -84,6 +90,28 @@ def algorithmic_cost(kind, V, rs, theta):
     if kind == "clover":
         return {"bytes": L * mat + V * 6 * mat, "flops": V * 6 * (12 * prod + 8 * adj)}
     return None
+
+
+def kernel_roofline(kind, ms_total, n, V, rs, theta, precision, dims):
+    """Roofline entry of one kernel from its event-measured average duration."""
+    c = algorithmic_cost(kind, V, rs, theta)
+    t = ms_total / n * 1e-3
+    peak_flops = VALU_FP64_TFLOPS if precision == "fp64" else VALU_FP32_TFLOPS
+    ridge = peak_flops * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if c["flops"] / c["bytes"] < ridge:
+        achieved = c["bytes"] / t / 1e9
+        rf = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    else:
+        achieved = c["flops"] / t / 1e12
+        rf = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak_flops, "unit": "TFLOP/s",
+              "frac": round(achieved / peak_flops, 4)}
+    rf["kernel"] = "k_" + kind
+    rf["avg_us"] = round(1e6 * t, 2)
+    rf["alg_bytes_per_launch"] = c["bytes"]
+    rf["alg_flops_per_launch"] = c["flops"]
+    rf["traffic"] = traffic_for(rf["kernel"], precision, dims)
+    return rf
 
 
 def run_gpu(args, precision, with_timing=True):
@@ -118,46 +146,24 @@ def run_gpu(args, precision, with_timing=True):
 
 
 def roofline(res, precision, theta):
+    """The dominant kernel's roofline (largest share of the step's kernel time)
+    and the per-kernel table."""
     rs = 8 if precision == "fp64" else 4
     V = res["V"]
     timing = res["timing"]
     if not timing:
-        return None, {}
+        return None, {}, []
     total = sum(ms for ms, _ in timing.values())
     kernels = {}
     for k, (ms, n) in timing.items():
-        c = algorithmic_cost(k, V, rs, theta)
-        ent = {"avg_us": 1e3 * ms / n, "launches": n, "share": ms / total}
-        if c:
-            t = ms / n * 1e-3
-            ent["alg_GBs"] = c["bytes"] / t / 1e9
-            ent["alg_TFLOPs"] = c["flops"] / t / 1e12
-        kernels[k] = ent
-    # the dominant kernel: the cooling sweep (both parities are one kernel)
-    groups = {}
-    for k, (ms, n) in timing.items():
-        g = "cool" if k.startswith("cool") else k
-        a = groups.setdefault(g, [0.0, 0])
-        a[0] += ms
-        a[1] += n
-    dom = max(groups, key=lambda g: groups[g][0])
-    ms, n = groups[dom]
-    t = ms / n * 1e-3
-    c = algorithmic_cost("cool_even" if dom == "cool" else dom, V, rs, theta)
-    peak_flops = VALU_FP64_TFLOPS if precision == "fp64" else VALU_FP32_TFLOPS
-    if dom == "cool" or c["flops"] / c["bytes"] < peak_flops * 1e12 / (HBM_PEAK_GBS * 1e9):
-        achieved = c["bytes"] / t / 1e9
-        rf = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    else:
-        achieved = c["flops"] / t / 1e12
-        rf = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak_flops, "unit": "TFLOP/s",
-              "frac": round(achieved / peak_flops, 4)}
-    rf["kernel"] = "k_cool" if dom == "cool" else "k_" + dom
-    rf["avg_us"] = round(1e6 * t, 2)
-    rf["share_of_step"] = round(ms / total, 3)
-    rf["traffic"] = traffic_for(rf["kernel"], precision, res["dims"])
-    return rf, kernels
+        kernels[k] = {"avg_us": round(1e3 * ms / n, 3), "launches": n, "share": round(ms / total, 4)}
+    costed = [k for k in timing if algorithmic_cost(k, V, rs, theta)]
+    rfs = []
+    for k in sorted(costed, key=lambda k: -timing[k][0]):
+        rf = kernel_roofline(k, timing[k][0], timing[k][1], V, rs, theta, precision, res["dims"])
+        rf["share_of_step"] = round(timing[k][0] / total, 3)
+        rfs.append(rf)
+    return rfs[0], kernels, rfs
 
 
 def traffic_for(kernel, precision, dims):
@@ -208,15 +214,15 @@ def served_mix(n, seed=6):
     return runs
 
 
-def served(args, capacity_lus):
+def served(args, capacity_lus, n_runs, load):
     """Continuous batching of the request mix arriving as a Poisson stream at
-    0.7x the single-run FP64 capacity, under an HBM budget small enough that
-    admission queues."""
+    `load` x the single-run FP64 capacity, under a fixed HBM budget (above 1x
+    the queue grows and admission waits for memory to free up)."""
     import numpy as np
     import paper_1311_1056_amd as cl
-    runs = served_mix(args.served_runs)
+    runs = served_mix(n_runs)
     work = np.array([4 * np.prod(r["dims"]) * r["n_steps"] for r in runs], dtype=float)
-    rate = 0.7 * capacity_lus / work.mean()  # runs per second
+    rate = load * capacity_lus / work.mean()  # runs per second
     arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / rate, len(runs)))
     srv = cl.Server(args.served_budget_mb << 20)
     results = []
@@ -242,10 +248,10 @@ def served(args, capacity_lus):
             "step_ms_p50": round(st["step_ms_p50"], 3), "step_ms_p99": round(st["step_ms_p99"], 3),
             "queue_wait_s_p50": round(st["wait_s_p50"], 3), "queue_wait_s_p99": round(st["wait_s_p99"], 3),
             "makespan_s": round(makespan, 2), "gpu_busy_s": round(st["busy_s"], 2),
-            "batch_steps": st["batch_steps"], "arrival_rate_runs_per_s": round(rate, 3),
+            "batch_steps": st["batch_steps"], "load": load, "arrival_rate_runs_per_s": round(rate, 3),
             "budget_bytes": args.served_budget_mb << 20,
             "mix": "6^4, 8^4, 12^4, 16^4, 8^3x16, 24^3x8; beta U[5.7,6.2]; theta U[0,2]; 50-500 steps; "
-                   "1-20 D1 cooling steps; eps0 U[1e-3,1e-2]; FP64 or mixed; Poisson arrivals at 0.7x capacity"}
+                   "1-20 D1 cooling steps; eps0 U[1e-3,1e-2]; FP64 or mixed; Poisson arrivals"}
 
 
 def copy_calibration(mib):
@@ -271,7 +277,7 @@ def main():
         copy_calibration(args.copy_calib)
         return
     res = run_gpu(args, args.precision)
-    rf, kernels = roofline(res, args.precision, args.theta)
+    rf, kernels, rfs = roofline(res, args.precision, args.theta)
     out = {
         "metric": METRIC,
         "value": round(res["value"], 1),
@@ -291,18 +297,20 @@ def main():
                    "lattice": args.dims.replace(",", "x"), "precision": args.precision,
                    "parallelism": "single GPU"},
         "roofline": rf,
+        "rooflines": rfs,
         "kernels": kernels,
         "observables_after": {"plaq": [res["obs"]["plaq"].real, res["obs"]["plaq"].imag],
                               "q": [res["obs"]["q"].real, res["obs"]["q"].imag], "d": res["obs"]["d"]},
     }
     if args.precision == "fp64" and not args.no_mixed:
         mx = run_gpu(args, "mixed")
-        mrf, mk = roofline(mx, "mixed", args.theta)
+        mrf, mk, mrfs = roofline(mx, "mixed", args.theta)
         out["mixed"] = {"value": round(mx["value"], 1), "ms_per_step": round(mx["ms_per_step"], 4),
                         "dtype": "f32 links/drift/cooling, f64 det renorm, reductions and control",
-                        "roofline": mrf}
+                        "roofline": mrf, "rooflines": mrfs}
     if args.served_runs > 0 and args.precision == "fp64":
-        out["served"] = served(args, res["value"])
+        out["served"] = served(args, res["value"], args.served_runs, 0.7)
+        out["served_overload"] = served(args, res["value"], max(1, args.served_runs // 2), 1.5)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

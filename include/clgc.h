@@ -156,8 +156,9 @@ cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_
 /* Kernel kinds reported by cl_timing_read. */
 typedef enum {
     CL_K_INIT = 0, CL_K_UNORM = 1, CL_K_PACK = 2, CL_K_CLOVER = 3, CL_K_DRIFT = 4, CL_K_UPDATE = 5,
-    CL_K_COOL_EVEN = 6, CL_K_COOL_ODD = 7, CL_K_GRADNORM = 8, CL_K_MEASURE = 9, CL_K_FINALIZE = 10,
-    CL_K_COUNT = 11
+    CL_K_COOL_OMEGA = 6,  /* even-site Omega of a cooling step */
+    CL_K_COOL_APPLY = 7,  /* both half-sweeps applied, odd-site Omega, every link written once */
+    CL_K_GRADNORM = 8, CL_K_MEASURE = 9, CL_K_FINALIZE = 10, CL_K_COUNT = 11
 } cl_kernel_kind;
 
 /* Benchmark instrumentation: while enabled, every kernel the lattice

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libclgc.so")
 CL_OK, CL_EINVAL, CL_ENOMEM, CL_EHIP, CL_ENONFINITE, CL_EBUDGET = 0, -1, -2, -3, -4, -5
 CL_FP64, CL_MIXED = 0, 1
 CL_ALPHA_FIXED, CL_ALPHA_UNORM, CL_ALPHA_GRAD = 0, 1, 2
-KERNEL_KINDS = ("init", "unorm", "pack", "clover", "drift", "update", "cool_even", "cool_odd", "gradnorm",
+KERNEL_KINDS = ("init", "unorm", "pack", "clover", "drift", "update", "cool_omega", "cool_apply", "gradnorm",
                 "measure", "finalize")
 
 

@@ -112,21 +112,21 @@ void recycle_marks(cl_lattice* lat)
     lat->marks.clear();
 }
 
-// launch `expr` (a hipError_t-returning launcher) bracketed by timing events
-// when the lattice records timings
+// launch `expr` (a hipError_t-returning launcher using lat->L); when the
+// lattice records timings the dispatch records a start and a stop event itself
 #define TIMED(lat, KIND, expr)                                                        \
     do {                                                                              \
-        hipEvent_t ea_ = nullptr, eb_ = nullptr;                                      \
         if ((lat)->timing) {                                                          \
-            ea_ = take_event(lat);                                                    \
-            eb_ = take_event(lat);                                                    \
+            hipEvent_t ea_ = take_event(lat), eb_ = take_event(lat);                  \
             if (!ea_ || !eb_) return fail(CL_EHIP, "hipEventCreate failed");         \
-            HIP_TRY(hipEventRecord(ea_, (lat)->stream));                              \
-        }                                                                             \
-        HIP_TRY(expr);                                                                \
-        if ((lat)->timing) {                                                          \
-            HIP_TRY(hipEventRecord(eb_, (lat)->stream));                              \
+            (lat)->L.ev_start = ea_;                                                  \
+            (lat)->L.ev_stop = eb_;                                                   \
+            const hipError_t te_ = (expr);                                            \
+            (lat)->L.ev_start = (lat)->L.ev_stop = nullptr;                           \
+            HIP_TRY(te_);                                                             \
             (lat)->marks.push_back({(KIND), ea_, eb_});                               \
+        } else {                                                                      \
+            HIP_TRY(expr);                                                            \
         }                                                                             \
     } while (0)
 
@@ -221,8 +221,8 @@ cl_status enqueue_cool(cl_lattice* lat, int n)
             TIMED(lat, CL_K_GRADNORM, launch_gradnorm(lat->L, lat->prec, i));
             TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_GRAD, i));
         }
-        TIMED(lat, CL_K_COOL_EVEN, launch_cool(lat->L, lat->prec, 0, i));
-        TIMED(lat, CL_K_COOL_ODD, launch_cool(lat->L, lat->prec, 1, i));
+        TIMED(lat, CL_K_COOL_OMEGA, launch_cool(lat->L, lat->prec, 0, i));
+        TIMED(lat, CL_K_COOL_APPLY, launch_cool(lat->L, lat->prec, 1, i));
         TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_COOL, i));
     }
     if (n > 0) lat->F_valid = false;

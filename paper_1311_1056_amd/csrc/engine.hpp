@@ -24,6 +24,8 @@ struct Launch {
     int blocks[NKIND];
     int nrun;
     hipStream_t stream;
+    hipEvent_t ev_start = nullptr;  // if set, the next launch records these two events
+    hipEvent_t ev_stop = nullptr;   // at its own start and end (kernel timing)
 };
 
 hipError_t launch_init(const Launch& L, int prec, int perturbed, double sx, double sy);
@@ -33,7 +35,8 @@ hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos
 hipError_t launch_clover(const Launch& L, int prec, int only_theta);
 hipError_t launch_drift(const Launch& L, int prec, bool theta);
 hipError_t launch_update(const Launch& L, int prec);
-hipError_t launch_cool(const Launch& L, int prec, int parity, int iter);
+// phase 0: even-site Omega (k_cool_omega); phase 1: apply both half-sweeps (k_cool_apply)
+hipError_t launch_cool(const Launch& L, int prec, int phase, int iter);
 hipError_t launch_gradnorm(const Launch& L, int prec, int iter);
 hipError_t launch_measure(const Launch& L, int prec);
 hipError_t launch_finalize(const Launch& L, int what, int iter);

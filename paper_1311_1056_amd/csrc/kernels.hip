@@ -11,6 +11,7 @@
 // kernels of a step and no grid-wide fence is needed inside a sweep.
 #include "engine.hpp"
 
+#include <hip/hip_ext.h>
 #include <math.h>
 
 namespace clgc {
@@ -300,8 +301,10 @@ __global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ 
 
 constexpr int kDriftLinks = kBlock / 2;
 
+// two waves per SIMD: the FP64 theta chain then spills ~20 registers, which
+// costs less than the memory latency a single wave per SIMD leaves exposed
 template <typename T, bool THETA>
-__global__ void __launch_bounds__(kBlock) k_drift(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+__global__ void __launch_bounds__(kBlock, 2) k_drift(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
 {
     __shared__ double lds[8];
     __shared__ cx<T> xch[9][kDriftLinks];
@@ -329,7 +332,9 @@ __global__ void __launch_bounds__(kBlock) k_drift(const BatchHdr* __restrict__ h
             const int nu = nn + (nn >= mu);
             const int P = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
             const int fo = dual_plane(P) * ra.V;
-#pragma unroll 1
+            // unrolled over the sign: a compile-time s selects the raw link or its
+            // adjugate without keeping both live
+#pragma unroll
             for (int si = 0; si < 2; ++si) {
                 const int s = si ? -1 : 1;
                 const Site d3 = site_move(ra, x, nu, s);
@@ -620,79 +625,179 @@ __device__ __forceinline__ mat3<T> mul_h(const mat3<T>& U, const herm3<T>& H)
     return r;
 }
 
-template <typename T, int PAR>
-__global__ void __launch_bounds__(kBlock) k_cool(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
-                                                 int iter)
+// One cooling step (an even, then an odd half-sweep) in two kernels.
+//
+// k_cool_omega: at every even site x, Omega_x = exp(-4 eps alpha G_x) and its
+// inverse from the links entering the step; the 18 reals are stored per even
+// site in the drift buffer, which is idle during cooling.  Nothing else is
+// written.
+//
+// k_cool_apply: at every odd site y, lane mu takes U_mu(y) and U_mu(y - mu),
+// applies the even-site transforms those links received (U_mu(y) ends at the
+// even site y + mu: U -> U Omega_{y+mu}^{-1}; U_mu(y - mu) starts at the even
+// site y - mu: U -> Omega_{y-mu} U), forms G_y from the transformed links,
+// Omega_y, and writes the two links with the odd transform applied.  Every
+// link is read and written once per cooling step, and each product is the one
+// the separate half-sweeps would evaluate, in the same order.
+
+// the 18 reals of (Omega, Omega^-1) of even site h: value j at OM[j * Vh + h]
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t omega_rsrc(const RunArgs& ra)
 {
-    __shared__ double lds[8];
+    const uint32_t bytes = 18u * (uint32_t)ra.Vh * (uint32_t)sizeof(T);
+    return __builtin_amdgcn_make_buffer_rsrc(ra.K, (short)0, (int)bytes, kBufferWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load_scalar(__amdgpu_buffer_rsrc_t rs, uint32_t lane_bytes, int elem_bytes)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)lane_bytes, elem_bytes, 0));
+    else
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)lane_bytes, elem_bytes, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store_scalar(__amdgpu_buffer_rsrc_t rs, uint32_t lane_bytes, int elem_bytes, T v)
+{
+    if constexpr (sizeof(T) == 8)
+    {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, (int)lane_bytes, elem_bytes, 0);
+    }
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rs, (int)lane_bytes, elem_bytes, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ herm3<T> load_herm(__amdgpu_buffer_rsrc_t rs, int h, int Vh, int j0)
+{
+    const uint32_t lane = (uint32_t)h * (uint32_t)sizeof(T);
+    const int es = Vh * (int)sizeof(T);
+    herm3<T> H;
+    H.d0 = buf_load_scalar<T>(rs, lane, (j0 + 0) * es);
+    H.d1 = buf_load_scalar<T>(rs, lane, (j0 + 1) * es);
+    H.d2 = buf_load_scalar<T>(rs, lane, (j0 + 2) * es);
+    H.u01 = {buf_load_scalar<T>(rs, lane, (j0 + 3) * es), buf_load_scalar<T>(rs, lane, (j0 + 4) * es)};
+    H.u02 = {buf_load_scalar<T>(rs, lane, (j0 + 5) * es), buf_load_scalar<T>(rs, lane, (j0 + 6) * es)};
+    H.u12 = {buf_load_scalar<T>(rs, lane, (j0 + 7) * es), buf_load_scalar<T>(rs, lane, (j0 + 8) * es)};
+    return H;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_herm(__amdgpu_buffer_rsrc_t rs, int h, int Vh, int j0, const herm3<T>& H)
+{
+    const uint32_t lane = (uint32_t)h * (uint32_t)sizeof(T);
+    const int es = Vh * (int)sizeof(T);
+    buf_store_scalar<T>(rs, lane, (j0 + 0) * es, H.d0);
+    buf_store_scalar<T>(rs, lane, (j0 + 1) * es, H.d1);
+    buf_store_scalar<T>(rs, lane, (j0 + 2) * es, H.d2);
+    buf_store_scalar<T>(rs, lane, (j0 + 3) * es, H.u01.re);
+    buf_store_scalar<T>(rs, lane, (j0 + 4) * es, H.u01.im);
+    buf_store_scalar<T>(rs, lane, (j0 + 5) * es, H.u02.re);
+    buf_store_scalar<T>(rs, lane, (j0 + 6) * es, H.u02.im);
+    buf_store_scalar<T>(rs, lane, (j0 + 7) * es, H.u12.re);
+    buf_store_scalar<T>(rs, lane, (j0 + 8) * es, H.u12.im);
+}
+
+// quad-reduced G (each lane holds its mu share) -> Omega = exp(coef TL(G)) and its inverse
+template <typename T>
+__device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm3<T>& Ei)
+{
+    G.d0 = quad_sum(G.d0);
+    G.d1 = quad_sum(G.d1);
+    G.d2 = quad_sum(G.d2);
+    G.u01 = {quad_sum(G.u01.re), quad_sum(G.u01.im)};
+    G.u02 = {quad_sum(G.u02.re), quad_sum(G.u02.im)};
+    G.u12 = {quad_sum(G.u12.re), quad_sum(G.u12.im)};
+    const T tr = (G.d0 + G.d1 + G.d2) * T(1.0 / 3.0);
+    herm3<T> A;
+    A.d0 = coef * (G.d0 - tr);
+    A.d1 = coef * (G.d1 - tr);
+    A.d2 = coef * (G.d2 - tr);
+    A.u01 = coef * G.u01;
+    A.u02 = coef * G.u02;
+    A.u12 = coef * G.u12;
+    herm_exp_pair(A, E, Ei);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cool_omega(const BatchHdr* __restrict__ hdr,
+                                                       const RunArgs* __restrict__ runs, int iter)
+{
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
     // block-uniform: this run still cools in this iteration
     if (iter < ra.n_cool && cr->status == ST_OK) {
-        double alpha_ad;
-        if (PAR == 0) {
-            alpha_ad = ra.mode == 1 ? ra.alpha / (cr->unorm / (4.0 * ra.V))
-                                    : (ra.mode == 2 ? cr->alpha_cur : ra.alpha);
-            if (lb == 0 && threadIdx.x == 0) {
-                if (ra.mode != 2) cr->alpha_cur = alpha_ad;
-                if (iter < kMaxCoolHist) {
-                    cr->hist_alpha[iter] = alpha_ad;
-                    cr->hist_un[iter] = cr->unorm;
-                    cr->hist_n = iter + 1;
-                }
+        const double alpha_ad = ra.mode == 1 ? ra.alpha / (cr->unorm / (4.0 * ra.V))
+                                             : (ra.mode == 2 ? cr->alpha_cur : ra.alpha);
+        if (lb == 0 && threadIdx.x == 0) {
+            if (ra.mode != 2) cr->alpha_cur = alpha_ad;
+            if (iter < kMaxCoolHist) {
+                cr->hist_alpha[iter] = alpha_ad;
+                cr->hist_un[iter] = cr->unorm;
+                cr->hist_n = iter + 1;
             }
-        } else {
-            alpha_ad = cr->alpha_cur;
         }
         const T coef = T(-4.0 * ra.eps_c * alpha_ad);
         const int h = tid >> 2, mu = tid & 3;
         const bool lane_ok = h < ra.Vh;
         herm3<T> G = h_zero<T>();
+        if (lane_ok) {
+            const Site x = site_coords(ra, 0, h);
+            const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
+            h_add_uudag(G, load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V));
+            h_sub_udagu(G, load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V));
+        }
+        herm3<T> E, Ei;
+        site_omega(G, coef, E, Ei);
+        if (lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
+    }
+    CLGC_END_BLOCKS
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cool_apply(const BatchHdr* __restrict__ hdr,
+                                                       const RunArgs* __restrict__ runs, int iter)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_COOL)
+    Ctrl* cr = ra.ctrl;
+    if (iter < ra.n_cool && cr->status == ST_OK) {
+        const T coef = T(-4.0 * ra.eps_c * cr->alpha_cur);
+        const int h = tid >> 2, mu = tid & 3;
+        const bool lane_ok = h < ra.Vh;
+        herm3<T> G = h_zero<T>();
         mat3<T> Uf, Ub;
         int of = 0, ob = 0;
-        const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
         if (lane_ok) {
-            const Site x = site_coords(ra, PAR, h);
-            const Site xb = site_move(ra, x, mu, -1);
-            of = (mu * 2 + PAR) * ra.Vh + h;
-            ob = link_off(ra, mu, xb);
-            Uf = load_mat(Uc, of, 4 * ra.V);
-            Ub = load_mat(Uc, ob, 4 * ra.V);
+            const Site y = site_coords(ra, 1, h);
+            const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
+            of = (mu * 2 + 1) * ra.Vh + h;
+            ob = link_off(ra, mu, yb);
+            const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
+            const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
+            Uf = mul_h(load_mat(Uc, of, 4 * ra.V), load_herm<T>(om, site_half(ra, yf), ra.Vh, 9));
+            Ub = h_mul(load_herm<T>(om, site_half(ra, yb), ra.Vh, 0), load_mat(Uc, ob, 4 * ra.V));
             h_add_uudag(G, Uf);
             h_sub_udagu(G, Ub);
         }
-        G.d0 = quad_sum(G.d0);
-        G.d1 = quad_sum(G.d1);
-        G.d2 = quad_sum(G.d2);
-        G.u01 = {quad_sum(G.u01.re), quad_sum(G.u01.im)};
-        G.u02 = {quad_sum(G.u02.re), quad_sum(G.u02.im)};
-        G.u12 = {quad_sum(G.u12.re), quad_sum(G.u12.im)};
+        herm3<T> E, Ei;
+        site_omega(G, coef, E, Ei);
         double un = 0.0;
         if (lane_ok) {
-            const T tr = (G.d0 + G.d1 + G.d2) * T(1.0 / 3.0);
-            herm3<T> A;
-            A.d0 = coef * (G.d0 - tr);
-            A.d1 = coef * (G.d1 - tr);
-            A.d2 = coef * (G.d2 - tr);
-            A.u01 = coef * G.u01;
-            A.u02 = coef * G.u02;
-            A.u12 = coef * G.u12;
-            herm3<T> E, Ei;
-            herm_exp_pair(A, E, Ei);
             const mat3<T> Nf = h_mul(E, Uf);
             const mat3<T> Nb = mul_h(Ub, Ei);
             cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
             store_mat(Uw, of, 4 * ra.V, Nf);
             store_mat(Uw, ob, 4 * ra.V, Nb);
-            if (PAR == 1) un = (double)m_norm2(Nf) + (double)m_norm2(Nb);
+            un = (double)m_norm2(Nf) + (double)m_norm2(Nb);
         }
-        if (PAR == 1) {
-            // every link is written exactly once by the odd half-sweep: the sum is
-            // the unitarity norm of the cooled configuration
-            double v[1] = {un};
-            block_reduce<1>(v, lds);
-            store_partials(ra, KIND_COOL, lb, v);
-        }
+        // every link is written exactly once: the sum is the unitarity norm of
+        // the cooled configuration
+        double v[1] = {un};
+        block_reduce<1>(v, lds);
+        store_partials(ra, KIND_COOL, lb, v);
     }
     CLGC_END_BLOCKS
 }
@@ -924,9 +1029,18 @@ inline int grid_of(const Launch& L, int kind)
 
 }  // namespace
 
-#define CLGC_LAUNCH(KERNEL, KIND, ...)                                                              \
-    hipLaunchKernelGGL(KERNEL, dim3(grid_of(L, KIND)), dim3(kBlock), 0, L.stream, L.hdr, L.runs, \
-                       ##__VA_ARGS__)
+// With L.ev_start / L.ev_stop set, the dispatch itself records the two events
+// at its start and end (hipExtLaunchKernelGGL), so the elapsed time is the
+// kernel's own execution time with no marker packets around it.
+#define CLGC_LAUNCH(KERNEL, KIND, ...)                                                                    \
+    do {                                                                                                  \
+        if (L.ev_start)                                                                                   \
+            hipExtLaunchKernelGGL(KERNEL, dim3(grid_of(L, KIND)), dim3(kBlock), 0, L.stream, L.ev_start,  \
+                                  L.ev_stop, 0, L.hdr, L.runs, ##__VA_ARGS__);                            \
+        else                                                                                              \
+            hipLaunchKernelGGL(KERNEL, dim3(grid_of(L, KIND)), dim3(kBlock), 0, L.stream, L.hdr, L.runs,  \
+                               ##__VA_ARGS__);                                                            \
+    } while (0)
 
 hipError_t launch_init(const Launch& L, int prec, int perturbed, double sx, double sy)
 {
@@ -982,14 +1096,14 @@ hipError_t launch_update(const Launch& L, int prec)
     return hipGetLastError();
 }
 
-hipError_t launch_cool(const Launch& L, int prec, int parity, int iter)
+hipError_t launch_cool(const Launch& L, int prec, int phase, int iter)
 {
     if (prec) {
-        if (parity) CLGC_LAUNCH((k_cool<float, 1>), KIND_COOL, iter);
-        else CLGC_LAUNCH((k_cool<float, 0>), KIND_COOL, iter);
+        if (phase) CLGC_LAUNCH(k_cool_apply<float>, KIND_COOL, iter);
+        else CLGC_LAUNCH(k_cool_omega<float>, KIND_COOL, iter);
     } else {
-        if (parity) CLGC_LAUNCH((k_cool<double, 1>), KIND_COOL, iter);
-        else CLGC_LAUNCH((k_cool<double, 0>), KIND_COOL, iter);
+        if (phase) CLGC_LAUNCH(k_cool_apply<double>, KIND_COOL, iter);
+        else CLGC_LAUNCH(k_cool_omega<double>, KIND_COOL, iter);
     }
     return hipGetLastError();
 }
@@ -1011,7 +1125,11 @@ hipError_t launch_measure(const Launch& L, int prec)
 hipError_t launch_finalize(const Launch& L, int what, int iter)
 {
     const int g = L.nrun > 0 ? L.nrun : 1;
-    hipLaunchKernelGGL(k_finalize, dim3(g), dim3(kBlock), 0, L.stream, L.hdr, L.runs, what, iter);
+    if (L.ev_start)
+        hipExtLaunchKernelGGL(k_finalize, dim3(g), dim3(kBlock), 0, L.stream, L.ev_start, L.ev_stop, 0, L.hdr,
+                              L.runs, what, iter);
+    else
+        hipLaunchKernelGGL(k_finalize, dim3(g), dim3(kBlock), 0, L.stream, L.hdr, L.runs, what, iter);
     return hipGetLastError();
 }
 

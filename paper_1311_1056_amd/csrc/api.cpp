@@ -1,7 +1,7 @@
 // api.cpp -- the C ABI of include/clgc.h on top of the kernels.
 //
 // A lattice lives entirely inside the caller's device buffer:
-//   [links U][drift K][clover F][partials][Ctrl][RunArgs][BatchHdr]
+//   [links U][drift K][clover F][partials][cooling partials][Ctrl][RunArgs][BatchHdr]
 // (K and F are adjacent so that together they can stage the host link
 // array in set/get_links).  Parameters reach the device through a one-thread
 // kernel that copies a RunArgs struct passed by value, so every call stays
@@ -57,6 +57,8 @@ Layout layout_of(const cl_lattice_desc& d)
     off = align256(off + 108 * V * rs);
     L.part = off;
     off = align256(off + sizeof(double) * kNumPartials * (size_t)maxb);
+    L.cpart = off;
+    off = align256(off + sizeof(double) * kMaxCoolBlocks);
     L.ctrl = off;
     off = align256(off + sizeof(Ctrl));
     L.args = off;
@@ -223,8 +225,10 @@ cl_status enqueue_cool(cl_lattice* lat, int n)
         }
         TIMED(lat, CL_K_COOL_OMEGA, launch_cool(lat->L, lat->prec, 0, i));
         TIMED(lat, CL_K_COOL_APPLY, launch_cool(lat->L, lat->prec, 1, i));
-        TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_COOL, i));
     }
+    // the next cooling step reduces the apply partials itself; only the last
+    // one is finalized (unitarity norm, history, status)
+    if (n > 0) TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_COOL, -1));
     if (n > 0) lat->F_valid = false;
     return CL_OK;
 }
@@ -321,6 +325,7 @@ cl_status cl_lattice_create(const cl_lattice_desc* desc, void* dev_buf, size_t b
     a.K = lat->base + lay.K;
     a.F = lat->base + lay.F;
     a.part = (double*)(lat->base + lay.part);
+    a.cpart = (double*)(lat->base + lay.cpart);
     a.ctrl = lat->d_ctrl;
     a.beta = desc->beta;
     a.th_re = desc->theta_re;

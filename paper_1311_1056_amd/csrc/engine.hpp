@@ -44,12 +44,20 @@ hipError_t launch_gather(const Launch& L, GatherRec* out);
 hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st);
 hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st);
 
+// Cooling kernels use at most kMaxCoolBlocks logical blocks per run (512
+// blocks of 256 threads at two waves per SIMD already fill the 256 CUs); a
+// block loops over contiguous chunks of 256 lanes.  The partial sums of one
+// cooling step then stay few enough that the next step's blocks reduce them
+// themselves, with no finalize launch in between.
+constexpr int kMaxCoolBlocks = 512;
+__host__ __device__ inline int cool_chunks_total(int V) { return (2 * V + kBlock - 1) / kBlock; }
+
 // logical blocks a run of V sites needs per kind
 inline void blocks_per_kind(int V, int out[NKIND])
 {
     out[KIND_LINK] = (4 * V + kBlock - 1) / kBlock;
     out[KIND_SITE] = (V + kBlock - 1) / kBlock;
-    out[KIND_COOL] = (2 * V + kBlock - 1) / kBlock;
+    out[KIND_COOL] = cool_chunks_total(V) < kMaxCoolBlocks ? cool_chunks_total(V) : kMaxCoolBlocks;
     const int Vh = V / 2;
     out[KIND_PLANE] = 12 * ((Vh + kBlock - 1) / kBlock);            // (region, plane, parity)
     out[KIND_DRIFT] = 8 * ((Vh + kBlock / 2 - 1) / (kBlock / 2));   // (region, mu, parity)

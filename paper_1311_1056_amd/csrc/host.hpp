@@ -26,7 +26,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // byte offsets of a lattice's pieces inside its device buffer
 struct Layout {
-    size_t U, K, F, part, ctrl, args, hdr, total;
+    size_t U, K, F, part, cpart, ctrl, args, hdr, total;
 };
 
 Layout layout_of(const cl_lattice_desc& d);

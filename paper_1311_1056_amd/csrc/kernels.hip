@@ -66,22 +66,21 @@ __device__ __forceinline__ void store_partials(const RunArgs& ra, int kind, int 
     }
 }
 
-// Fixed-order sum (or max) of one partial array of the run; valid in thread 0.
-// Each thread issues eight independent loads before combining them, so the
-// gather costs a few memory round trips rather than one per loop trip.
+// Fixed-order sum (or max) of n partials at p_in; valid in thread 0.  Each
+// thread issues eight independent loads before combining them, so the gather
+// costs a few memory round trips rather than one per loop trip.
 template <bool MAX = false>
-__device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, int j, double* lds)
+__device__ __forceinline__ double gather_values(const double* p_in, int n, double* lds)
 {
     typedef __attribute__((address_space(1))) const double* gcd;
-    const int nblk = ra.nblk[kind];
-    const gcd p = (gcd)(ra.part + (size_t)j * nblk);
+    const gcd p = (gcd)p_in;
     double acc = 0.0;
-    for (int base = 0; base < nblk; base += 8 * kBlock) {
+    for (int base = 0; base < n; base += 8 * kBlock) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = base + u * kBlock + (int)threadIdx.x;
-            v[u] = i < nblk ? p[i] : 0.0;
+            v[u] = i < n ? p[i] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = MAX ? (isnan(v[u]) || isnan(acc) ? NAN : fmax(acc, v[u])) : acc + v[u];
@@ -89,6 +88,27 @@ __device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, i
     double r[1] = {acc};
     block_reduce<1, MAX>(r, lds);
     return r[0];
+}
+
+// partial j of every logical block of one kind
+template <bool MAX = false>
+__device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, int j, double* lds)
+{
+    const int nblk = ra.nblk[kind];
+    return gather_values<MAX>(ra.part + (size_t)j * nblk, nblk, lds);
+}
+
+// the cooling step's unitarity-norm partials, summed and broadcast to every
+// thread of the block
+__device__ __forceinline__ double gather_cool_all(const RunArgs& ra, double* lds)
+{
+    __shared__ double s_all;
+    const double v = gather_values(ra.cpart, ra.nblk[KIND_COOL], lds);
+    if (threadIdx.x == 0) s_all = v;
+    __syncthreads();
+    const double r = s_all;
+    __syncthreads();
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -725,33 +745,45 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cool_omega(const BatchHdr* __restrict__ hdr,
                                                        const RunArgs* __restrict__ runs, int iter)
 {
+    __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
     // block-uniform: this run still cools in this iteration
     if (iter < ra.n_cool && cr->status == ST_OK) {
-        const double alpha_ad = ra.mode == 1 ? ra.alpha / (cr->unorm / (4.0 * ra.V))
+        // unitarity norm entering the step: from the finalized update (step 0) or
+        // reduced here from the previous step's apply partials (every block
+        // reduces the same <= 512 values in the same order)
+        const double un = iter == 0 ? cr->unorm : gather_cool_all(ra, lds);
+        const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
                                              : (ra.mode == 2 ? cr->alpha_cur : ra.alpha);
         if (lb == 0 && threadIdx.x == 0) {
             if (ra.mode != 2) cr->alpha_cur = alpha_ad;
+            cr->unorm = un;
+            if (!isfinite(un)) cr->status = ST_NONFINITE;
             if (iter < kMaxCoolHist) {
                 cr->hist_alpha[iter] = alpha_ad;
-                cr->hist_un[iter] = cr->unorm;
+                cr->hist_un[iter] = un;
                 cr->hist_n = iter + 1;
             }
         }
         const T coef = T(-4.0 * ra.eps_c * alpha_ad);
-        const int h = tid >> 2, mu = tid & 3;
-        const bool lane_ok = h < ra.Vh;
-        herm3<T> G = h_zero<T>();
-        if (lane_ok) {
-            const Site x = site_coords(ra, 0, h);
-            const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-            h_add_uudag(G, load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V));
-            h_sub_udagu(G, load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V));
+        const int nch = cool_chunks_total(ra.V);
+        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
+        for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+            const int t = c * kBlock + (int)threadIdx.x;
+            const int h = t >> 2, mu = t & 3;
+            const bool lane_ok = h < ra.Vh;
+            herm3<T> G = h_zero<T>();
+            if (lane_ok) {
+                const Site x = site_coords(ra, 0, h);
+                const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
+                h_add_uudag(G, load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V));
+                h_sub_udagu(G, load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V));
+            }
+            herm3<T> E, Ei;
+            site_omega(G, coef, E, Ei);
+            if (lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
         }
-        herm3<T> E, Ei;
-        site_omega(G, coef, E, Ei);
-        if (lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
     }
     CLGC_END_BLOCKS
 }
@@ -765,39 +797,44 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const BatchHdr* __restric
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool && cr->status == ST_OK) {
         const T coef = T(-4.0 * ra.eps_c * cr->alpha_cur);
-        const int h = tid >> 2, mu = tid & 3;
-        const bool lane_ok = h < ra.Vh;
-        herm3<T> G = h_zero<T>();
-        mat3<T> Uf, Ub;
-        int of = 0, ob = 0;
-        if (lane_ok) {
-            const Site y = site_coords(ra, 1, h);
-            const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
-            of = (mu * 2 + 1) * ra.Vh + h;
-            ob = link_off(ra, mu, yb);
-            const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-            const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
-            Uf = mul_h(load_mat(Uc, of, 4 * ra.V), load_herm<T>(om, site_half(ra, yf), ra.Vh, 9));
-            Ub = h_mul(load_herm<T>(om, site_half(ra, yb), ra.Vh, 0), load_mat(Uc, ob, 4 * ra.V));
-            h_add_uudag(G, Uf);
-            h_sub_udagu(G, Ub);
-        }
-        herm3<T> E, Ei;
-        site_omega(G, coef, E, Ei);
+        const int nch = cool_chunks_total(ra.V);
+        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
         double un = 0.0;
-        if (lane_ok) {
-            const mat3<T> Nf = h_mul(E, Uf);
-            const mat3<T> Nb = mul_h(Ub, Ei);
-            cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
-            store_mat(Uw, of, 4 * ra.V, Nf);
-            store_mat(Uw, ob, 4 * ra.V, Nb);
-            un = (double)m_norm2(Nf) + (double)m_norm2(Nb);
+        for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+            const int t = c * kBlock + (int)threadIdx.x;
+            const int h = t >> 2, mu = t & 3;
+            const bool lane_ok = h < ra.Vh;
+            herm3<T> G = h_zero<T>();
+            mat3<T> Uf, Ub;
+            int of = 0, ob = 0;
+            if (lane_ok) {
+                const Site y = site_coords(ra, 1, h);
+                const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
+                of = (mu * 2 + 1) * ra.Vh + h;
+                ob = link_off(ra, mu, yb);
+                const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
+                const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
+                Uf = mul_h(load_mat(Uc, of, 4 * ra.V), load_herm<T>(om, site_half(ra, yf), ra.Vh, 9));
+                Ub = h_mul(load_herm<T>(om, site_half(ra, yb), ra.Vh, 0), load_mat(Uc, ob, 4 * ra.V));
+                h_add_uudag(G, Uf);
+                h_sub_udagu(G, Ub);
+            }
+            herm3<T> E, Ei;
+            site_omega(G, coef, E, Ei);
+            if (lane_ok) {
+                const mat3<T> Nf = h_mul(E, Uf);
+                const mat3<T> Nb = mul_h(Ub, Ei);
+                cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
+                store_mat(Uw, of, 4 * ra.V, Nf);
+                store_mat(Uw, ob, 4 * ra.V, Nb);
+                un += (double)m_norm2(Nf) + (double)m_norm2(Nb);
+            }
         }
         // every link is written exactly once: the sum is the unitarity norm of
         // the cooled configuration
         double v[1] = {un};
         block_reduce<1>(v, lds);
-        store_partials(ra, KIND_COOL, lb, v);
+        if (threadIdx.x == 0) ra.cpart[lb] = v[0];
     }
     CLGC_END_BLOCKS
 }
@@ -950,11 +987,13 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const BatchHdr* __restrict_
             break;
         }
         case FIN_COOL: {
-            if (!ok || iter >= ra.n_cool) break;
-            const double tot = gather_partials(ra, KIND_COOL, 0, lds);
+            // iter < 0: the run's own last cooling step (runs in a batch differ)
+            const int it = iter < 0 ? ra.n_cool - 1 : iter;
+            if (!ok || it < 0 || it >= ra.n_cool) break;
+            const double tot = gather_values(ra.cpart, ra.nblk[KIND_COOL], lds);
             if (threadIdx.x == 0) {
                 c->unorm = tot;
-                if (iter + 1 <= kMaxCoolHist) c->hist_un[iter + 1] = tot;
+                if (it + 1 <= kMaxCoolHist) c->hist_un[it + 1] = tot;
                 if (!isfinite(tot)) c->status = ST_NONFINITE;
             }
             break;

@@ -71,6 +71,8 @@ struct RunArgs {
     void* F;           // clover field
     void* K;           // drift
     double* part;      // per-logical-block partials: part[j * nblk + b]
+    double* cpart;     // the cooling step's unitarity-norm partials (<= kMaxCoolBlocks), kept
+                       // apart so a D_2 gradient pass between two steps cannot overwrite them
     Ctrl* ctrl;
     double beta, th_re, th_im;
     uint64_t seed;

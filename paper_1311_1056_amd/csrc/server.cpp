@@ -247,8 +247,8 @@ cl_status enqueue_group_step(cl_server* s, int g, int max_nc, bool any_theta, bo
         }
         HIP_TRY(launch_cool(L, g, 0, i));
         HIP_TRY(launch_cool(L, g, 1, i));
-        HIP_TRY(launch_finalize(L, FIN_COOL, i));
     }
+    if (max_nc > 0) HIP_TRY(launch_finalize(L, FIN_COOL, -1));  // each run's last cooling step
     HIP_TRY(launch_gather(L, s->d_gather[g]));
     return CL_OK;
 }

@@ -81,10 +81,16 @@ def algorithmic_cost(kind, V, rs, theta):
         return {"bytes": L * 2 * mat + (V // 2) * 18 * rs,
                 "flops": L * 2 * hprod + (V // 2) * (8 * 54 + hexp)}
     if kind == "drift":
-        wil = 6 * (2 * prod + adj) + 2 * prod + adj
-        top = 6 * (14 * prod + 2 * adj) if theta else 0
+        # one walk per loop along the staple P = e1 e2 e3: Wilson part P and
+        # adj(P) (2 products, 3 adjugates, 2 complex axpys of 9 entries); with
+        # the theta term the transported clover adds, per corner d2 and d3, two
+        # products, an adjugate and the det(R)^-1 scaling (~122 flops), plus the
+        # staple product R, four insertion products and two scalings.  Per link:
+        # e0 A + B adj(e0) and the traceless part.
+        axpy, scale, transport = 2 * 9 * 8, 2 * 9 * 6, 2 * prod + adj + 122
+        loop = (6 * prod + 3 * adj + 2 * transport + axpy + scale) if theta else (2 * prod + 3 * adj + axpy)
         byt = L * (mat + mat) + (V * 6 * mat if theta else 0)  # links + K out (+ F in)
-        return {"bytes": byt, "flops": L * (wil + top)}
+        return {"bytes": byt, "flops": L * (6 * loop + 2 * prod + adj)}
     if kind == "update":
         return {"bytes": L * 3 * mat, "flops": L * (3 * prod + 600)}
     if kind == "clover":

@@ -60,7 +60,7 @@ inline void blocks_per_kind(int V, int out[NKIND])
     out[KIND_COOL] = cool_chunks_total(V) < kMaxCoolBlocks ? cool_chunks_total(V) : kMaxCoolBlocks;
     const int Vh = V / 2;
     out[KIND_PLANE] = 12 * ((Vh + kBlock - 1) / kBlock);            // (region, plane, parity)
-    out[KIND_DRIFT] = 8 * ((Vh + kBlock / 2 - 1) / (kBlock / 2));   // (region, mu, parity)
+    out[KIND_DRIFT] = 8 * ((Vh + kBlock - 1) / kBlock);             // (region, mu, parity)
 }
 
 constexpr int kNumPartials = 7;  // the most partial values any kernel publishes

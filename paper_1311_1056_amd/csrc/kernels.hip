@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(const BatchHdr* __restrict__ hd
 // x in the (mu, nu) plane of (L - L^{-1})
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+__global__ void __launch_bounds__(kBlock, 2) k_clover(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
                                                    int only_theta)
 {
     CLGC_FOR_BLOCKS(KIND_PLANE)
@@ -280,22 +280,42 @@ __global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ 
         const Site xmm = site_move(ra, x, mu, -1), xmn = site_move(ra, x, nu, -1);
         const Site xmmpn = site_move(ra, xmm, nu, +1), xmmmn = site_move(ra, xmm, nu, -1);
         const Site xmnpm = site_move(ra, xmn, mu, +1);
-        const mat3<T> Umx = ldU<T>(ra, mu, x), Unx = ldU<T>(ra, nu, x);
-        const mat3<T> Umxmm = ldU<T>(ra, mu, xmm), Unxmn = ldU<T>(ra, nu, xmn);
-        mat3<T> F = m_zero<T>();
-        mat3<T> L;
-        // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
-        L = (Umx * ldU<T>(ra, nu, xpm)) * m_adj(Unx * ldU<T>(ra, mu, xpn));
-        F = F + (L - m_adj(L));
-        // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
-        L = Unx * (m_adj(ldU<T>(ra, nu, xmm) * ldU<T>(ra, mu, xmmpn)) * Umxmm);
-        F = F + (L - m_adj(L));
-        // [U_nu(x-mu-nu) U_mu(x-mu)]^{-1} U_mu(x-mu-nu) U_nu(x-nu)
-        L = m_adj(ldU<T>(ra, nu, xmmmn) * Umxmm) * (ldU<T>(ra, mu, xmmmn) * Unxmn);
-        F = F + (L - m_adj(L));
-        // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
-        L = m_adj(Unxmn) * ((ldU<T>(ra, mu, xmn) * ldU<T>(ra, nu, xmnpm)) * m_adj(Umx));
-        F = F + (L - m_adj(L));
+        mat3<T> F, L;
+        if constexpr (sizeof(T) == 8) {
+            // FP64: each leaf loads its own four links (repeats hit in cache) and
+            // the scheduling barriers keep the next leaf's loads from being
+            // hoisted, which holds two waves per SIMD without spilling
+            // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
+            L = (ldU<T>(ra, mu, x) * ldU<T>(ra, nu, xpm)) * m_adj(ldU<T>(ra, nu, x) * ldU<T>(ra, mu, xpn));
+            F = L - m_adj(L);
+            __builtin_amdgcn_sched_barrier(0);
+            // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
+            L = ldU<T>(ra, nu, x) * (m_adj(ldU<T>(ra, nu, xmm) * ldU<T>(ra, mu, xmmpn)) * ldU<T>(ra, mu, xmm));
+            F = F + (L - m_adj(L));
+            __builtin_amdgcn_sched_barrier(0);
+            // [U_nu(x-mu-nu) U_mu(x-mu)]^{-1} U_mu(x-mu-nu) U_nu(x-nu)
+            L = m_adj(ldU<T>(ra, nu, xmmmn) * ldU<T>(ra, mu, xmm)) * (ldU<T>(ra, mu, xmmmn) * ldU<T>(ra, nu, xmn));
+            F = F + (L - m_adj(L));
+            __builtin_amdgcn_sched_barrier(0);
+            // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
+            L = m_adj(ldU<T>(ra, nu, xmn)) * ((ldU<T>(ra, mu, xmn) * ldU<T>(ra, nu, xmnpm)) * m_adj(ldU<T>(ra, mu, x)));
+            F = F + (L - m_adj(L));
+        } else {
+            const mat3<T> Umx = ldU<T>(ra, mu, x), Unx = ldU<T>(ra, nu, x);
+            const mat3<T> Umxmm = ldU<T>(ra, mu, xmm), Unxmn = ldU<T>(ra, nu, xmn);
+            // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
+            L = (Umx * ldU<T>(ra, nu, xpm)) * m_adj(Unx * ldU<T>(ra, mu, xpn));
+            F = L - m_adj(L);
+            // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
+            L = Unx * (m_adj(ldU<T>(ra, nu, xmm) * ldU<T>(ra, mu, xmmpn)) * Umxmm);
+            F = F + (L - m_adj(L));
+            // [U_nu(x-mu-nu) U_mu(x-mu)]^{-1} U_mu(x-mu-nu) U_nu(x-nu)
+            L = m_adj(ldU<T>(ra, nu, xmmmn) * Umxmm) * (ldU<T>(ra, mu, xmmmn) * Unxmn);
+            F = F + (L - m_adj(L));
+            // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
+            L = m_adj(Unxmn) * ((ldU<T>(ra, mu, xmn) * ldU<T>(ra, nu, xmnpm)) * m_adj(Umx));
+            F = F + (L - m_adj(L));
+        }
         store_mat((cx<T>*)ra.F, tid_f, 6 * ra.V, F);
     }
     CLGC_END_BLOCKS
@@ -304,136 +324,129 @@ __global__ void __launch_bounds__(kBlock) k_clover(const BatchHdr* __restrict__ 
 // ---------------------------------------------------------------------------
 // drift
 //
-// For link (x, mu) each of the six loops through it is Gamma = e0 e1 e2 e3
-// with corners d0 = x, d1 = x+mu, d2 = x+mu+s nu, d3 = x+s nu.  With the
-// staple A = e1 e2 e3 (d1 -> d0) and its inverse A' = e3' e2' e1':
-//   Khat_W     = (i beta/3) TL( e0 sum A - sum A' e0' ),
-//   Khat_theta = theta/(128 pi^2) TL( e0 sum sigma I + sum sigma J e0' ),
-//   I = X1 e1e2e3 + e1 X2 e2e3 + e1e2 X3 e3 + e1e2e3 X0     (Horner, 8 products),
-//   J = X0 e3'e2'e1' + e3' X3 e2'e1' + e3'e2' X2 e1' + e3'e2'e1' X1   (8 products),
-// X_k the dual clover matrix of the loop's plane at d_k, sigma = s sign(nu - mu).
-// A logical block owns 128 links: waves 0-1 accumulate the forward chains
-// Lacc = sum (cb A + ct sigma I) and form e0 Lacc, waves 2-3 the backward
-// chains Racc = sum (cb A' - ct sigma J) and form Racc e0'; the backward half
-// hands its matrix over through LDS and the forward half stores
-// Khat = TL(e0 Lacc - Racc e0').  Splitting by chain (not by lane) keeps every
-// wave on one code path and halves the live matrices per lane.
+// For link (x, mu) each of the six loops through it is e0 e1 e2 e3 with
+// corners d0 = x, d1 = x+mu, d2 = x+mu+s nu, d3 = x+s nu (e0 = U_mu(x)) and
+// staple P = e1 e2 e3 (d1 -> d0).  With X_k the dual clover matrix of the
+// loop's plane at d_k, the theta term inserts X_k at each corner of the loop
+// and of its inverse in turn:
+//   I = X1 e1e2e3 + e1 X2 e2e3 + e1e2 X3 e3 + e1e2e3 X0,
+//   J = X0 e3'e2'e1' + e3' X3 e2'e1' + e3'e2' X2 e1' + e3'e2'e1' X1
+// (' the inverse), and
+//   Khat = TL( e0 sum (cb P + cts I) - sum (cb P' - cts J) e0' ),
+// cb = i beta/3, cts = sigma theta/(128 pi^2), sigma = s sign(nu - mu) times
+// the sign of the dual plane.  With the paths R_1 = 1, R_2 = e1, R_3 = e1 e2
+// from d1 to the corners and the transported clover Q = sum_k R_k X_k R_k^-1,
+//   I = Q P + P X0,    J = X0 P' + P' Q,
+// so one walk along the staple gives both chains.  Inverses are adjugates
+// (the inverse on SL(3,C)); adj(AB) = adj(B) adj(A) makes P' = adj(P) exact,
+// and R_k^-1 = adj(R_k)/det(R_k) keeps both identities exact for any links.
+// One lane per link loads each of a loop's seven matrices once.
 
-constexpr int kDriftLinks = kBlock / 2;
+// Q += R X R^-1 with R^-1 = adj(R) / det(R)
+template <typename T>
+__device__ __forceinline__ void add_transported(mat3<T>& Q, const mat3<T>& R, const mat3<T>& X)
+{
+    const mat3<T> Ra = m_adj(R);
+    // det R from the first row of R and the first column of adj(R)
+    const cx<T> d = cfma(R.e[0][2], Ra.e[2][0], cfma(R.e[0][1], Ra.e[1][0], R.e[0][0] * Ra.e[0][0]));
+    const T r = T(1) / fma(d.re, d.re, d.im * d.im);
+    const cx<T> di = {d.re * r, -d.im * r};
+    const mat3<T> RX = R * X;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> t = RX.e[i][0] * Ra.e[0][j];
+            t = cfma(RX.e[i][1], Ra.e[1][j], t);
+            t = cfma(RX.e[i][2], Ra.e[2][j], t);
+            Q.e[i][j] = cfma(t, di, Q.e[i][j]);
+        }
+}
 
-// two waves per SIMD: the FP64 theta chain then spills ~20 registers, which
-// costs less than the memory latency a single wave per SIMD leaves exposed
+// FP64 with the theta term runs one wave per SIMD: its walk needs ~440
+// registers, which then live in the VGPRs and AGPRs without touching scratch
+// (at two waves it spills hundreds of bytes per lane)
 template <typename T, bool THETA>
-__global__ void __launch_bounds__(kBlock, 2) k_drift(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_drift(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
 {
     __shared__ double lds[8];
-    __shared__ cx<T> xch[9][kDriftLinks];
     CLGC_FOR_BLOCKS(KIND_DRIFT)
-    // logical block -> (region of 128 half-indices, direction, parity): the eight
+    // logical block -> (region of 256 half-indices, direction, parity): the eight
     // (mu, parity) blocks of a region are adjacent, so one XCD covers all the
     // links of a contiguous slab of sites
     const int mu = (lb & 7) >> 1, p = lb & 1;
-    const int h = (lb >> 3) * kDriftLinks + (int)(threadIdx.x & (kDriftLinks - 1));
+    const int h = (lb >> 3) * kBlock + (int)threadIdx.x;
     const int l = (mu * 2 + p) * ra.Vh + h;
-    const int back = threadIdx.x >= kDriftLinks;  // wave-uniform
-    const bool ok = h < ra.Vh;
-    mat3<T> M;
-    if (ok) {
+    double kn2 = 0.0;
+    if (h < ra.Vh) {
         const Site x = site_coords(ra, p, h);
         const Site d1 = site_move(ra, x, mu, +1);
         const cx<T> cb = {T(0), T(ra.beta / 3.0)};
+        const cx<T> mcb = {T(0), T(-ra.beta / 3.0)};
         const double tn = 1.0 / (128.0 * M_PI * M_PI);
         const cx<T> ct = {T(ra.th_re * tn), T(ra.th_im * tn)};
+        const cx<T>* __restrict__ Ub = (const cx<T>*)ra.U;
         const cx<T>* __restrict__ Fb = (const cx<T>*)ra.F;
-        const int fs = 6 * ra.V;
-        mat3<T> acc = m_zero<T>();
+        const int us = 4 * ra.V, fs = 6 * ra.V;
+        // block-uniform: a batch can mix runs with and without a theta term
+        const bool th = THETA && ra.has_theta;
+        // A = sum (cb P + cts I),  B = sum (cts J - cb P'):  Khat = TL(e0 A + B e0')
+        mat3<T> A = m_zero<T>(), B = m_zero<T>();
 #pragma unroll 1
         for (int nn = 0; nn < 3; ++nn) {
             const int nu = nn + (nn >= mu);
-            const int P = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
-            const int fo = dual_plane(P) * ra.V;
+            const int Pl = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
+            const int fo = dual_plane(Pl) * ra.V;
             // unrolled over the sign: a compile-time s selects the raw link or its
-            // adjugate without keeping both live
+            // adjugate
 #pragma unroll
             for (int si = 0; si < 2; ++si) {
                 const int s = si ? -1 : 1;
+                // FP64: scheduling barriers keep the walk's stages (and the two
+                // signs) from pulling every load forward at once
+                if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
                 const Site d3 = site_move(ra, x, nu, s);
                 const Site d2 = site_move(ra, d1, nu, s);
-                // raw links of the loop: e1 = l1 (s>0) or l1^-1, e2 = l2^-1, e3 = l3^-1 (s>0) or l3
-                const int o1 = link_off(ra, nu, s > 0 ? d1 : d2);
-                const int o2 = link_off(ra, mu, d3);
-                const int o3 = link_off(ra, nu, s > 0 ? x : d3);
-                const cx<T>* __restrict__ Ub = (const cx<T>*)ra.U;
-                const int us = 4 * ra.V;
-                const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(P));
-                const cx<T> cts = {sig * ct.re, sig * ct.im};
-                // block-uniform: a batch can mix runs with and without a theta term
-                const bool th = THETA && ra.has_theta;
-                if (!back) {
-                    // forward chain from d1 to d0
-                    mat3<T> e3 = load_mat(Ub, o3, us);
+                // e1 = U_nu(d1) (s>0) or U_nu(d2)^-1, e2 = U_mu(d3)^-1, e3 = U_nu(x)^-1 (s>0) or U_nu(d3)
+                mat3<T> e1 = load_mat(Ub, link_off(ra, nu, s > 0 ? d1 : d2), us);
+                if (s < 0) e1 = m_adj(e1);
+                if (!th) {
+                    mat3<T> Pm = e1 * m_adj(load_mat(Ub, link_off(ra, mu, d3), us));
+                    mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
                     if (s > 0) e3 = m_adj(e3);
-                    const mat3<T> e2 = m_adj(load_mat(Ub, o2, us));
-                    mat3<T> Pm = e2 * e3;
-                    if (!th) {
-                        mat3<T> e1 = load_mat(Ub, o1, us);
-                        if (s < 0) e1 = m_adj(e1);
-                        m_axpy(acc, cb, e1 * Pm);
-                    } else {
-                        mat3<T> I = load_mat(Fb, fo + link_off(ra, 0, d3), fs) * e3;
-                        m_mac(I, e3, load_mat(Fb, fo + p * ra.Vh + h, fs));
-                        mat3<T> I2 = load_mat(Fb, fo + link_off(ra, 0, d2), fs) * Pm;
-                        m_mac(I2, e2, I);
-                        mat3<T> e1 = load_mat(Ub, o1, us);
-                        if (s < 0) e1 = m_adj(e1);
-                        Pm = e1 * Pm;
-                        I = load_mat(Fb, fo + link_off(ra, 0, d1), fs) * Pm;
-                        m_mac(I, e1, I2);
-                        m_axpy(acc, cb, Pm);
-                        m_axpy(acc, cts, I);
-                    }
+                    Pm = Pm * e3;
+                    m_axpy(A, cb, Pm);
+                    m_axpy(B, mcb, m_adj(Pm));
                 } else {
-                    // backward chain from d0 to d1 (inverse links)
-                    mat3<T> e1i = load_mat(Ub, o1, us);
-                    if (s > 0) e1i = m_adj(e1i);
-                    const mat3<T> e2i = load_mat(Ub, o2, us);
-                    mat3<T> Rm = e2i * e1i;
-                    if (!th) {
-                        mat3<T> e3i = load_mat(Ub, o3, us);
-                        if (s < 0) e3i = m_adj(e3i);
-                        m_axpy(acc, cb, e3i * Rm);
-                    } else {
-                        mat3<T> J = load_mat(Fb, fo + link_off(ra, 0, d2), fs) * e1i;
-                        m_mac(J, e1i, load_mat(Fb, fo + link_off(ra, 0, d1), fs));
-                        mat3<T> J2 = load_mat(Fb, fo + link_off(ra, 0, d3), fs) * Rm;
-                        m_mac(J2, e2i, J);
-                        mat3<T> e3i = load_mat(Ub, o3, us);
-                        if (s < 0) e3i = m_adj(e3i);
-                        Rm = e3i * Rm;
-                        J = load_mat(Fb, fo + p * ra.Vh + h, fs) * Rm;
-                        m_mac(J, e3i, J2);
-                        m_axpy(acc, cb, Rm);
-                        const cx<T> mcts = {-cts.re, -cts.im};
-                        m_axpy(acc, mcts, J);
-                    }
+                    const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(Pl));
+                    const cx<T> cts = {sig * ct.re, sig * ct.im};
+                    mat3<T> Q = load_mat(Fb, fo + link_off(ra, 0, d1), fs);
+                    add_transported(Q, e1, load_mat(Fb, fo + link_off(ra, 0, d2), fs));
+                    if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+                    const mat3<T> R = e1 * m_adj(load_mat(Ub, link_off(ra, mu, d3), us));
+                    add_transported(Q, R, load_mat(Fb, fo + link_off(ra, 0, d3), fs));
+                    if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+                    mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
+                    if (s > 0) e3 = m_adj(e3);
+                    const mat3<T> Pm = R * e3;
+                    const mat3<T> Pa = m_adj(Pm);
+                    m_axpy(A, cb, Pm);
+                    m_axpy(B, mcb, Pa);
+                    Q = m_scale(Q, cts);
+                    m_mac(A, Q, Pm);
+                    m_mac(B, Pa, Q);
+                    const mat3<T> X0 = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
+                    m_mac(A, Pm, X0);
+                    m_mac(B, X0, Pa);
                 }
             }
         }
-        const mat3<T> e0 = load_mat((const cx<T>*)ra.U, l, 4 * ra.V);
-        M = back ? acc * m_adj(e0) : e0 * acc;
-    }
-    const int slot = threadIdx.x & (kDriftLinks - 1);
-    if (back && ok) {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) xch[e][slot] = M.e[e / 3][e % 3];
-    }
-    __syncthreads();
-    double kn2 = 0.0;
-    if (!back && ok) {
-#pragma unroll
-        for (int e = 0; e < 9; ++e) M.e[e / 3][e % 3] = M.e[e / 3][e % 3] - xch[e][slot];
+        if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+        const mat3<T> e0 = load_mat(Ub, l, us);
+        mat3<T> M = e0 * A;
+        m_mac(M, B, m_adj(e0));
         const mat3<T> K = m_traceless(M);
-        store_mat((cx<T>*)ra.K, l, 4 * ra.V, K);
+        store_mat((cx<T>*)ra.K, l, us, K);
         kn2 = 0.5 * (double)m_norm2(K);
         if (!isfinite(kn2)) kn2 = INFINITY;
     }

@@ -233,17 +233,17 @@ cl_status enqueue_cool(cl_lattice* lat, int n)
     return CL_OK;
 }
 
-// Capture one full step (drift, update, n_cool cooling steps and their
+// Capture n_rep full steps (drift, update, n_cool cooling steps and their
 // finalize kernels) into a graph.  Kernels read every parameter from the
 // device RunArgs / Ctrl, so the graph stays valid while parameters change;
 // only the launch sequence (n_cool, D_2 mode, theta) keys it.
-cl_status ensure_step_graph(cl_lattice* lat, int n_cool)
+cl_status ensure_graph(cl_lattice* lat, int n_cool, int n_rep, hipGraphExec_t& slot, int (&slot_key)[3])
 {
     const int key[3] = {n_cool, lat->args.mode, lat->has_theta ? 1 : 0};
-    if (lat->step_graph && std::memcmp(key, lat->graph_key, sizeof key) == 0) return CL_OK;
-    if (lat->step_graph) {
-        HIP_TRY(hipGraphExecDestroy(lat->step_graph));
-        lat->step_graph = nullptr;
+    if (slot && std::memcmp(key, slot_key, sizeof key) == 0) return CL_OK;
+    if (slot) {
+        HIP_TRY(hipGraphExecDestroy(slot));
+        slot = nullptr;
     }
     if (!lat->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&lat->cap_stream, hipStreamNonBlocking));
     const hipStream_t user = lat->stream;
@@ -254,8 +254,10 @@ cl_status ensure_step_graph(cl_lattice* lat, int n_cool)
     cl_status st = CL_OK;
     hipError_t e = hipStreamBeginCapture(lat->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = enqueue_step(lat);
-        if (st == CL_OK) st = enqueue_cool(lat, n_cool);
+        for (int r = 0; r < n_rep && st == CL_OK; ++r) {
+            st = enqueue_step(lat);
+            if (st == CL_OK) st = enqueue_cool(lat, n_cool);
+        }
         e = hipStreamEndCapture(lat->cap_stream, &g);
     }
     lat->stream = user;
@@ -270,8 +272,8 @@ cl_status ensure_step_graph(cl_lattice* lat, int n_cool)
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(CL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    lat->step_graph = ex;
-    std::memcpy(lat->graph_key, key, sizeof key);
+    slot = ex;
+    std::memcpy(slot_key, key, sizeof key);
     return CL_OK;
 }
 
@@ -378,6 +380,7 @@ cl_status cl_lattice_destroy(cl_lattice* lat)
     recycle_marks(lat);
     for (hipEvent_t ev : lat->pool) (void)hipEventDestroy(ev);
     if (lat->step_graph) (void)hipGraphExecDestroy(lat->step_graph);
+    if (lat->multi_graph) (void)hipGraphExecDestroy(lat->multi_graph);
     if (lat->cap_stream) (void)hipStreamDestroy(lat->cap_stream);
     delete lat;
     if (e != hipSuccess) return fail(CL_EHIP, "cl_lattice_destroy: %s", hipGetErrorString(e));
@@ -489,8 +492,17 @@ cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_
         }
         return CL_OK;
     }
-    if ((st = ensure_step_graph(lat, cool->n_steps)) != CL_OK) return st;
-    for (int i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(lat->step_graph, lat->stream));
+    // whole blocks of kGraphSteps steps from one graph (the gap between two graph
+    // launches is paid once per block), the remainder from the one-step graph
+    const int blocks = n_steps / kGraphSteps, rest = n_steps % kGraphSteps;
+    if (blocks > 0) {
+        if ((st = ensure_graph(lat, cool->n_steps, kGraphSteps, lat->multi_graph, lat->multi_key)) != CL_OK) return st;
+        for (int i = 0; i < blocks; ++i) HIP_TRY(hipGraphLaunch(lat->multi_graph, lat->stream));
+    }
+    if (rest > 0) {
+        if ((st = ensure_graph(lat, cool->n_steps, 1, lat->step_graph, lat->graph_key)) != CL_OK) return st;
+        for (int i = 0; i < rest; ++i) HIP_TRY(hipGraphLaunch(lat->step_graph, lat->stream));
+    }
     lat->F_valid = false;
     return CL_OK;
 }

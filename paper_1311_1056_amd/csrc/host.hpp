@@ -34,6 +34,10 @@ cl_status check_desc(const cl_lattice_desc* d);
 
 }  // namespace clgc
 
+// steps captured into the block graph that cl_run_steps replays (the idle
+// gap between two graph launches is then paid once per block)
+constexpr int kGraphSteps = 8;
+
 struct cl_lattice {
     cl_lattice_desc desc;
     int prec;
@@ -57,8 +61,11 @@ struct cl_lattice {
     };
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
-    // one captured CL step (update + cooling), replayed by cl_run_steps
+    // one captured CL step (update + cooling) and a block of kGraphSteps of
+    // them, replayed by cl_run_steps (captured on a private stream)
     hipStream_t cap_stream;
     hipGraphExec_t step_graph;
     int graph_key[3];   // n_cool, mode, has_theta of the captured step
+    hipGraphExec_t multi_graph;
+    int multi_key[3];
 };

@@ -29,18 +29,20 @@ def say(*a):
     print(*a, flush=True)
 
 
-def test_graph_replay_matches_eager(cl):
-    """cl_run_steps replays a captured step graph; it must give exactly what
-    individual launches give, replay after replay."""
+@pytest.mark.parametrize("n_steps", [2, 11])
+def test_graph_replay_matches_eager(cl, n_steps):
+    """cl_run_steps replays captured graphs (blocks of 8 steps, then single
+    steps); it must give exactly what individual launches give, replay after
+    replay."""
     dims = (4, 4, 4, 8)
     a = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=9)
     b = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=9)
     a.init(True)
     b.init(True)
     for rep in range(3):
-        a.run_steps(2, 1e-2, True, 3, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+        a.run_steps(n_steps, 1e-2, True, 3, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
         ma = a.measure()  # eager work and a synchronisation between replays
-        for _ in range(2):
+        for _ in range(n_steps):
             b.langevin_step(1e-2, adaptive=True, sync=False)
             b.gauge_cool(3, 1e-2, 1.0, cl.CL_ALPHA_UNORM, sync=False)
         mb = b.measure()

@@ -132,9 +132,12 @@ void recycle_marks(cl_lattice* lat)
         }                                                                             \
     } while (0)
 
+// the device RunArgs (read by batched launches and kept for them) and the copy
+// that travels in the kernel arguments of this lattice's launches
 cl_status push_args(cl_lattice* lat)
 {
     HIP_TRY(launch_write_args(lat->d_args, lat->args, lat->stream));
+    lat->L.one = lat->args;
     return CL_OK;
 }
 
@@ -234,13 +237,19 @@ cl_status enqueue_cool(cl_lattice* lat, int n)
 }
 
 // Capture n_rep full steps (drift, update, n_cool cooling steps and their
-// finalize kernels) into a graph.  Kernels read every parameter from the
-// device RunArgs / Ctrl, so the graph stays valid while parameters change;
-// only the launch sequence (n_cool, D_2 mode, theta) keys it.
-cl_status ensure_graph(cl_lattice* lat, int n_cool, int n_rep, hipGraphExec_t& slot, int (&slot_key)[3])
+// finalize kernels) into a graph.  The kernels take the run's parameters from
+// their kernel arguments (a copy of RunArgs) and its evolving state from the
+// device Ctrl block, so a graph is keyed by the launch sequence (n_cool, D_2
+// mode, theta) and by the RunArgs it was captured with.
+cl_status ensure_graph(cl_lattice* lat, int n_cool, int n_rep, hipGraphExec_t& slot, GraphKey& slot_key)
 {
-    const int key[3] = {n_cool, lat->args.mode, lat->has_theta ? 1 : 0};
-    if (slot && std::memcmp(key, slot_key, sizeof key) == 0) return CL_OK;
+    GraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.n_cool = n_cool;
+    key.mode = lat->args.mode;
+    key.theta = lat->has_theta ? 1 : 0;
+    key.args = lat->args;
+    if (slot && std::memcmp(&key, &slot_key, sizeof key) == 0) return CL_OK;
     if (slot) {
         HIP_TRY(hipGraphExecDestroy(slot));
         slot = nullptr;
@@ -273,7 +282,7 @@ cl_status ensure_graph(cl_lattice* lat, int n_cool, int n_rep, hipGraphExec_t& s
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(CL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     slot = ex;
-    std::memcpy(slot_key, key, sizeof key);
+    std::memcpy(&slot_key, &key, sizeof key);
     return CL_OK;
 }
 
@@ -352,6 +361,8 @@ cl_status cl_lattice_create(const cl_lattice_desc* desc, void* dev_buf, size_t b
     lat->L.runs = lat->d_args;
     for (int k = 0; k < NKIND; ++k) lat->L.blocks[k] = a.nblk[k];
     lat->L.nrun = 1;
+    lat->L.fast = 1;
+    lat->L.one = a;
     lat->L.stream = lat->stream;
 
     hipError_t e = hipMemcpyAsync(lat->d_hdr, &hdr, sizeof hdr, hipMemcpyHostToDevice, lat->stream);

@@ -23,6 +23,8 @@ struct Launch {
     const RunArgs* runs;
     int blocks[NKIND];
     int nrun;
+    int fast = 0;       // a single run whose RunArgs travel in the kernel arguments
+    RunArgs one{};      // that copy (kept equal to the device RunArgs by the host)
     hipStream_t stream;
     hipEvent_t ev_start = nullptr;  // if set, the next launch records these two events
     hipEvent_t ev_stop = nullptr;   // at its own start and end (kernel timing)

@@ -34,6 +34,13 @@ cl_status check_desc(const cl_lattice_desc* d);
 
 }  // namespace clgc
 
+// what a captured step graph depends on: the launch sequence and the RunArgs
+// copy its kernel arguments carry (compared bytewise; zero-filled first)
+struct GraphKey {
+    int n_cool, mode, theta, pad;
+    clgc::RunArgs args;
+};
+
 // steps captured into the block graph that cl_run_steps replays (the idle
 // gap between two graph launches is then paid once per block)
 constexpr int kGraphSteps = 8;
@@ -65,7 +72,7 @@ struct cl_lattice {
     // them, replayed by cl_run_steps (captured on a private stream)
     hipStream_t cap_stream;
     hipGraphExec_t step_graph;
-    int graph_key[3];   // n_cool, mode, has_theta of the captured step
+    GraphKey graph_key;
     hipGraphExec_t multi_graph;
-    int multi_key[3];
+    GraphKey multi_key;
 };

@@ -121,18 +121,37 @@ __device__ __forceinline__ double gather_cool_all(const RunArgs& ra, double* lds
 // and clover matrices a block re-reads, stay in one L2.  Grids are launched as
 // a multiple of eight (or grid-stride with a multiple-of-eight stride), so the
 // XCD of a logical slot never changes.
+// The body between CLGC_FOR_BLOCKS and CLGC_END_BLOCKS runs once per logical
+// block (ra, lb, tid); it is written once, as a lambda, and each kernel
+// instance inlines it into one of two loops: FAST, a single run whose RunArgs
+// sit in the kernel arguments, or a batch, where the run of each block is
+// looked up in the device tables.
 #define CLGC_FOR_BLOCKS(KIND)                                                  \
-    const int total_ = hdr->total[KIND];                                       \
-    const int q_ = (total_ + kXcds - 1) / kXcds;                               \
-    for (int gb0_ = blockIdx.x; gb0_ < kXcds * q_; gb0_ += gridDim.x) {        \
-        const int gb_ = (gb0_ % kXcds) * q_ + gb0_ / kXcds;                    \
-        if (gb_ >= total_) continue;                                           \
-        const int run_ = find_run(hdr, KIND, gb_);                             \
-        const RunArgs& ra = runs[run_];                                        \
-        const int lb = gb_ - hdr->begin[KIND][run_];                           \
-        const int tid = lb * kBlock + (int)threadIdx.x;
+    constexpr int kind_ = (KIND);                                              \
+    auto body_ = [&](const RunArgs& ra, const int lb) __attribute__((always_inline)) { \
+        const int tid = lb * kBlock + (int)threadIdx.x;                        \
+        (void)tid;
 
-#define CLGC_END_BLOCKS }
+#define CLGC_END_BLOCKS                                                        \
+    };                                                                         \
+    if constexpr (FAST) {                                                      \
+        const int total_ = ka.one.nblk[kind_];                                 \
+        const int q_ = (total_ + kXcds - 1) / kXcds;                           \
+        for (int gb0_ = blockIdx.x; gb0_ < kXcds * q_; gb0_ += gridDim.x) {    \
+            const int gb_ = (gb0_ % kXcds) * q_ + gb0_ / kXcds;                \
+            if (gb_ < total_) body_(ka.one, gb_);                              \
+        }                                                                      \
+    } else {                                                                   \
+        const BatchHdr* __restrict__ hdr_ = ka.hdr;                            \
+        const int total_ = hdr_->total[kind_];                                 \
+        const int q_ = (total_ + kXcds - 1) / kXcds;                           \
+        for (int gb0_ = blockIdx.x; gb0_ < kXcds * q_; gb0_ += gridDim.x) {    \
+            const int gb_ = (gb0_ % kXcds) * q_ + gb0_ / kXcds;                \
+            if (gb_ >= total_) continue;                                       \
+            const int run_ = find_run(hdr_, kind_, gb_);                       \
+            body_(ka.runs[run_], gb_ - hdr_->begin[kind_][run_]);              \
+        }                                                                      \
+    }
 
 // decompose a link index l in [0, 4V): l = (mu * 2 + p) * Vh + h
 __device__ __forceinline__ void link_decompose(const RunArgs& ra, int l, int& mu, int& p, int& h)
@@ -152,8 +171,8 @@ __device__ __forceinline__ mat3<T> ldU(const RunArgs& ra, int mu, const Site& s)
 // ---------------------------------------------------------------------------
 // initial configuration
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_init(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_init(const KArgs ka,
                                                  int perturbed, double sx, double sy)
 {
     __shared__ double lds[8];
@@ -206,8 +225,8 @@ __global__ void __launch_bounds__(kBlock) k_init(const BatchHdr* __restrict__ hd
 }
 
 // unitarity norm of the current links (after links are written from the host)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_unorm(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_unorm(const KArgs ka)
 {
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_LINK)
@@ -220,8 +239,8 @@ __global__ void __launch_bounds__(kBlock) k_unorm(const BatchHdr* __restrict__ h
 }
 
 // host AoS (double, lexicographic) <-> device SoA (T, checkerboard)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_unpack(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_unpack(const KArgs ka,
                                                    const double* __restrict__ aos)
 {
     CLGC_FOR_BLOCKS(KIND_LINK)
@@ -238,8 +257,8 @@ __global__ void __launch_bounds__(kBlock) k_unpack(const BatchHdr* __restrict__ 
     CLGC_END_BLOCKS
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pack(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_pack(const KArgs ka,
                                                  const void* __restrict__ field, double* __restrict__ aos)
 {
     CLGC_FOR_BLOCKS(KIND_LINK)
@@ -262,8 +281,8 @@ __global__ void __launch_bounds__(kBlock) k_pack(const BatchHdr* __restrict__ hd
 // clover field: F_{mu nu}(x) = sum over the four counter-clockwise leaves L at
 // x in the (mu, nu) plane of (L - L^{-1})
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock, 2) k_clover(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs,
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock, 2) k_clover(const KArgs ka,
                                                    int only_theta)
 {
     CLGC_FOR_BLOCKS(KIND_PLANE)
@@ -366,8 +385,8 @@ __device__ __forceinline__ void add_transported(mat3<T>& Q, const mat3<T>& R, co
 // FP64 with the theta term runs one wave per SIMD: its walk needs ~440
 // registers, which then live in the VGPRs and AGPRs without touching scratch
 // (at two waves it spills hundreds of bytes per lane)
-template <typename T, bool THETA>
-__global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_drift(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+template <typename T, bool THETA, bool FAST>
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_drift(const KArgs ka)
 {
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_DRIFT)
@@ -460,8 +479,8 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
 // Langevin update: U <- exp(i (eps K + sqrt(eps) eta_a lambda_a)) U, then
 // U <- U det(U)^{-1/3} in FP64.
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_update(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
 {
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_LINK)
@@ -754,9 +773,8 @@ __device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm
     herm_exp_pair(A, E, Ei);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cool_omega(const BatchHdr* __restrict__ hdr,
-                                                       const RunArgs* __restrict__ runs, int iter)
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
 {
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_COOL)
@@ -801,9 +819,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const BatchHdr* __restric
     CLGC_END_BLOCKS
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cool_apply(const BatchHdr* __restrict__ hdr,
-                                                       const RunArgs* __restrict__ runs, int iter)
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
 {
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_COOL)
@@ -854,9 +871,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const BatchHdr* __restric
 
 // D_2 = mean over (a, x) of |f_ax| on the configuration entering a cooling
 // step, f_ax = 2 Tr(lambda_a G_x); sets alpha_cur = alpha / D_2.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gradnorm(const BatchHdr* __restrict__ hdr,
-                                                     const RunArgs* __restrict__ runs, int iter)
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_gradnorm(const KArgs ka, int iter)
 {
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_SITE)
@@ -890,8 +906,8 @@ __global__ void __launch_bounds__(kBlock) k_gradnorm(const BatchHdr* __restrict_
 // measurement: plaquette traces (and of their inverses, for the Wilson
 // action), topological charge density from the clover field, unitarity norm
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_measure(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs)
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_measure(const KArgs ka)
 {
     __shared__ double lds[7 * 4];
     CLGC_FOR_BLOCKS(KIND_SITE)
@@ -941,12 +957,11 @@ __global__ void __launch_bounds__(kBlock) k_measure(const BatchHdr* __restrict__
 // finalize: one block per run sums (or maxes) the partials of the kernel that
 // just ran, in a fixed order, and updates the run's control block.
 
-__global__ void __launch_bounds__(kBlock) k_finalize(const BatchHdr* __restrict__ hdr,
-                                                     const RunArgs* __restrict__ runs, int what, int iter)
+template <bool FAST>
+__global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, int iter)
 {
     __shared__ double lds[8];
-    for (int r = blockIdx.x; r < hdr->nrun; r += gridDim.x) {
-        const RunArgs& ra = runs[r];
+    auto fin_ = [&](const RunArgs& ra) __attribute__((always_inline)) {
         Ctrl* c = ra.ctrl;
         const bool ok = c->status == ST_OK;
         switch (what) {
@@ -1031,14 +1046,19 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const BatchHdr* __restrict_
         default:
             break;
         }
+    };
+    if constexpr (FAST) {
+        if (blockIdx.x == 0) fin_(ka.one);
+    } else {
+        for (int r = blockIdx.x; r < ka.hdr->nrun; r += gridDim.x) fin_(ka.runs[r]);
     }
 }
 
 // compact per-run status for the host after a batched step
-__global__ void k_gather(const BatchHdr* __restrict__ hdr, const RunArgs* __restrict__ runs, GatherRec* out)
+__global__ void k_gather(const KArgs ka, GatherRec* out)
 {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < hdr->nrun; r += gridDim.x * blockDim.x) {
-        const Ctrl* c = runs[r].ctrl;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ka.hdr->nrun; r += gridDim.x * blockDim.x) {
+        const Ctrl* c = ka.runs[r].ctrl;
         GatherRec g;
         g.step = c->step;
         g.status = c->status;
@@ -1084,110 +1104,133 @@ inline int grid_of(const Launch& L, int kind)
 // With L.ev_start / L.ev_stop set, the dispatch itself records the two events
 // at its start and end (hipExtLaunchKernelGGL), so the elapsed time is the
 // kernel's own execution time with no marker packets around it.
-#define CLGC_LAUNCH(KERNEL, KIND, ...)                                                                    \
+#define CLGC_LAUNCH_1(KERNEL, KIND, ...)                                                                  \
     do {                                                                                                  \
+        const KArgs ka_ = make_kargs(L);                                                                  \
         if (L.ev_start)                                                                                   \
             hipExtLaunchKernelGGL(KERNEL, dim3(grid_of(L, KIND)), dim3(kBlock), 0, L.stream, L.ev_start,  \
-                                  L.ev_stop, 0, L.hdr, L.runs, ##__VA_ARGS__);                            \
+                                  L.ev_stop, 0, ka_, ##__VA_ARGS__);                                      \
         else                                                                                              \
-            hipLaunchKernelGGL(KERNEL, dim3(grid_of(L, KIND)), dim3(kBlock), 0, L.stream, L.hdr, L.runs,  \
+            hipLaunchKernelGGL(KERNEL, dim3(grid_of(L, KIND)), dim3(kBlock), 0, L.stream, ka_,            \
                                ##__VA_ARGS__);                                                            \
     } while (0)
 
+// KERNEL names its instance with FAST_, bound here to the launch's path
+#define CLGC_LAUNCH(KERNEL, KIND, ...)                                                                    \
+    do {                                                                                                  \
+        if (L.fast) {                                                                                     \
+            constexpr bool FAST_ = true;                                                                  \
+            CLGC_LAUNCH_1(KERNEL, KIND, ##__VA_ARGS__);                                                   \
+        } else {                                                                                          \
+            constexpr bool FAST_ = false;                                                                 \
+            CLGC_LAUNCH_1(KERNEL, KIND, ##__VA_ARGS__);                                                   \
+        }                                                                                                 \
+    } while (0)
+
+KArgs make_kargs(const Launch& L)
+{
+    KArgs k;
+    k.hdr = L.hdr;
+    k.runs = L.runs;
+    k.one = L.one;
+    return k;
+}
+
 hipError_t launch_init(const Launch& L, int prec, int perturbed, double sx, double sy)
 {
-    if (prec) CLGC_LAUNCH(k_init<float>, KIND_LINK, perturbed, sx, sy);
-    else CLGC_LAUNCH(k_init<double>, KIND_LINK, perturbed, sx, sy);
+    if (prec) CLGC_LAUNCH((k_init<float, FAST_>), KIND_LINK, perturbed, sx, sy);
+    else CLGC_LAUNCH((k_init<double, FAST_>), KIND_LINK, perturbed, sx, sy);
     return hipGetLastError();
 }
 
 hipError_t launch_unorm(const Launch& L, int prec)
 {
-    if (prec) CLGC_LAUNCH(k_unorm<float>, KIND_LINK);
-    else CLGC_LAUNCH(k_unorm<double>, KIND_LINK);
+    if (prec) CLGC_LAUNCH((k_unorm<float, FAST_>), KIND_LINK);
+    else CLGC_LAUNCH((k_unorm<double, FAST_>), KIND_LINK);
     return hipGetLastError();
 }
 
 hipError_t launch_unpack(const Launch& L, int prec, const double* aos)
 {
-    if (prec) CLGC_LAUNCH(k_unpack<float>, KIND_LINK, aos);
-    else CLGC_LAUNCH(k_unpack<double>, KIND_LINK, aos);
+    if (prec) CLGC_LAUNCH((k_unpack<float, FAST_>), KIND_LINK, aos);
+    else CLGC_LAUNCH((k_unpack<double, FAST_>), KIND_LINK, aos);
     return hipGetLastError();
 }
 
 hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos)
 {
-    if (prec) CLGC_LAUNCH(k_pack<float>, KIND_LINK, field, aos);
-    else CLGC_LAUNCH(k_pack<double>, KIND_LINK, field, aos);
+    if (prec) CLGC_LAUNCH((k_pack<float, FAST_>), KIND_LINK, field, aos);
+    else CLGC_LAUNCH((k_pack<double, FAST_>), KIND_LINK, field, aos);
     return hipGetLastError();
 }
 
 hipError_t launch_clover(const Launch& L, int prec, int only_theta)
 {
-    if (prec) CLGC_LAUNCH(k_clover<float>, KIND_PLANE, only_theta);
-    else CLGC_LAUNCH(k_clover<double>, KIND_PLANE, only_theta);
+    if (prec) CLGC_LAUNCH((k_clover<float, FAST_>), KIND_PLANE, only_theta);
+    else CLGC_LAUNCH((k_clover<double, FAST_>), KIND_PLANE, only_theta);
     return hipGetLastError();
 }
 
 hipError_t launch_drift(const Launch& L, int prec, bool theta)
 {
     if (prec) {
-        if (theta) CLGC_LAUNCH((k_drift<float, true>), KIND_DRIFT);
-        else CLGC_LAUNCH((k_drift<float, false>), KIND_DRIFT);
+        if (theta) CLGC_LAUNCH((k_drift<float, true, FAST_>), KIND_DRIFT);
+        else CLGC_LAUNCH((k_drift<float, false, FAST_>), KIND_DRIFT);
     } else {
-        if (theta) CLGC_LAUNCH((k_drift<double, true>), KIND_DRIFT);
-        else CLGC_LAUNCH((k_drift<double, false>), KIND_DRIFT);
+        if (theta) CLGC_LAUNCH((k_drift<double, true, FAST_>), KIND_DRIFT);
+        else CLGC_LAUNCH((k_drift<double, false, FAST_>), KIND_DRIFT);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_update(const Launch& L, int prec)
 {
-    if (prec) CLGC_LAUNCH(k_update<float>, KIND_LINK);
-    else CLGC_LAUNCH(k_update<double>, KIND_LINK);
+    if (prec) CLGC_LAUNCH((k_update<float, FAST_>), KIND_LINK);
+    else CLGC_LAUNCH((k_update<double, FAST_>), KIND_LINK);
     return hipGetLastError();
 }
 
 hipError_t launch_cool(const Launch& L, int prec, int phase, int iter)
 {
     if (prec) {
-        if (phase) CLGC_LAUNCH(k_cool_apply<float>, KIND_COOL, iter);
-        else CLGC_LAUNCH(k_cool_omega<float>, KIND_COOL, iter);
+        if (phase) CLGC_LAUNCH((k_cool_apply<float, FAST_>), KIND_COOL, iter);
+        else CLGC_LAUNCH((k_cool_omega<float, FAST_>), KIND_COOL, iter);
     } else {
-        if (phase) CLGC_LAUNCH(k_cool_apply<double>, KIND_COOL, iter);
-        else CLGC_LAUNCH(k_cool_omega<double>, KIND_COOL, iter);
+        if (phase) CLGC_LAUNCH((k_cool_apply<double, FAST_>), KIND_COOL, iter);
+        else CLGC_LAUNCH((k_cool_omega<double, FAST_>), KIND_COOL, iter);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_gradnorm(const Launch& L, int prec, int iter)
 {
-    if (prec) CLGC_LAUNCH(k_gradnorm<float>, KIND_SITE, iter);
-    else CLGC_LAUNCH(k_gradnorm<double>, KIND_SITE, iter);
+    if (prec) CLGC_LAUNCH((k_gradnorm<float, FAST_>), KIND_SITE, iter);
+    else CLGC_LAUNCH((k_gradnorm<double, FAST_>), KIND_SITE, iter);
     return hipGetLastError();
 }
 
 hipError_t launch_measure(const Launch& L, int prec)
 {
-    if (prec) CLGC_LAUNCH(k_measure<float>, KIND_SITE);
-    else CLGC_LAUNCH(k_measure<double>, KIND_SITE);
+    if (prec) CLGC_LAUNCH((k_measure<float, FAST_>), KIND_SITE);
+    else CLGC_LAUNCH((k_measure<double, FAST_>), KIND_SITE);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Launch& L, int what, int iter)
 {
-    const int g = L.nrun > 0 ? L.nrun : 1;
+    const int g = L.fast ? 1 : (L.nrun > 0 ? L.nrun : 1);
+    const KArgs ka = make_kargs(L);
+    auto* const kern = L.fast ? k_finalize<true> : k_finalize<false>;
     if (L.ev_start)
-        hipExtLaunchKernelGGL(k_finalize, dim3(g), dim3(kBlock), 0, L.stream, L.ev_start, L.ev_stop, 0, L.hdr,
-                              L.runs, what, iter);
+        hipExtLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, L.stream, L.ev_start, L.ev_stop, 0, ka, what, iter);
     else
-        hipLaunchKernelGGL(k_finalize, dim3(g), dim3(kBlock), 0, L.stream, L.hdr, L.runs, what, iter);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, L.stream, ka, what, iter);
     return hipGetLastError();
 }
 
 hipError_t launch_gather(const Launch& L, GatherRec* out)
 {
-    hipLaunchKernelGGL(k_gather, dim3(1), dim3(kBlock), 0, L.stream, L.hdr, L.runs, out);
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(kBlock), 0, L.stream, make_kargs(L), out);
     return hipGetLastError();
 }
 

@@ -90,6 +90,17 @@ struct BatchHdr {
     int begin[NKIND][kMaxRuns + 1];
 };
 
+// What every kernel of the path receives: the batch tables in device memory
+// and, when a single lattice is launched through the lattice API (the FAST
+// instance of each kernel), a copy of its RunArgs in the kernel arguments, so
+// that a block reaches its field pointers without first reading the tables
+// (two dependent memory round trips fewer at every kernel start).
+struct KArgs {
+    const BatchHdr* hdr;
+    const RunArgs* runs;
+    RunArgs one;
+};
+
 // ---------------------------------------------------------------------------
 // index arithmetic
 

@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 32^4, theta-point and cooling-mode legs")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--served-runs", type=int, default=256, help="runs in the served mix (0: skip)")
     ap.add_argument("--served-budget-mb", type=int, default=2048)
@@ -187,19 +189,48 @@ def traffic_for(kernel, precision, dims):
     return ent.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args):
+    """The FP64 oracle timed on the host: a bounded sample of the bench workload
+    on all threads, plus the two small configurations (4^4 fixed-eps D_0 and
+    8^4 adaptive D_1) on all threads and on one thread."""
     import numpy as np
     import oracle
     dims = tuple(int(x) for x in args.dims.split(","))
     V = int(np.prod(dims))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     U = oracle.init_links(dims, 3, 0.3, 0.05)
     t0 = time.perf_counter()
     oracle.run(dims, U, args.beta, args.theta, 3, args.cpu_steps, 1e-2, True, args.ncool, 1e-2, 1.0, 1)
     dt = time.perf_counter() - t0
+    small = {}
+    for name, (cd, beta, seed, nst, eps0, adaptive, nc, mode) in {
+            "4x4x4x4_fixed_eps_D0": ((4, 4, 4, 4), 5.7, 1, 20, 1e-3, False, 5, 0),
+            "8x8x8x8_adaptive_D1": ((8, 8, 8, 8), 6.0, 2, 3, 1e-2, True, 10, 1)}.items():
+        rec = {}
+        for nth in (threads, 1):
+            oracle.set_threads(nth)
+            Uc = oracle.init_links(cd, seed, 0.3, 0.05)
+            t1 = time.perf_counter()
+            oracle.run(cd, Uc, beta, 0.0, seed, nst, eps0, adaptive, nc, eps0, 1.0, mode)
+            rec[f"threads_{nth}"] = round(4 * int(np.prod(cd)) * nst / (time.perf_counter() - t1), 1)
+        small[name] = rec
+    oracle.set_threads(threads)
     return {"value": 4 * V * args.cpu_steps / dt, "unit": "link-updates/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{args.cpu_steps} steps (CL update + {args.ncool} cooling steps + measurement each) of the "
-                      f"same {'x'.join(map(str, dims))} workload, FP64, {threads} OpenMP threads, {dt:.1f} s"}
+                      f"same {'x'.join(map(str, dims))} workload, FP64, {threads} OpenMP threads, {dt:.1f} s",
+            "small_configs_link_updates_per_s": small}
 
 
 SERVED_SHAPES = [(6, 6, 6, 6), (8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (8, 8, 8, 16), (24, 24, 24, 8)]
@@ -260,6 +291,143 @@ def served(args, capacity_lus, n_runs, load):
                    "1-20 D1 cooling steps; eps0 U[1e-3,1e-2]; FP64 or mixed; Poisson arrivals"}
 
 
+def with_args(args, **kw):
+    d = dict(vars(args))
+    d.update(kw)
+    return argparse.Namespace(**d)
+
+
+def large_lattice(args):
+    """32^4 FP64: 604 MB of links, more than the 256 MB Infinity Cache, so every
+    sweep streams from HBM."""
+    a = with_args(args, dims="32,32,32,32", steps=5, warmup=2)
+    res = run_gpu(a, "fp64")
+    rf, kernels, rfs = roofline(res, "fp64", args.theta)
+    return {"lattice": "32x32x32x32", "value": round(res["value"], 1), "unit": "link-updates/s",
+            "ms_per_step": round(res["ms_per_step"], 4), "steps": a.steps, "roofline": rf, "rooflines": rfs}
+
+
+def theta_points(args):
+    """The 16^4 workload at theta = 0, 0.5 and 2 (theta = 1 is the main line)."""
+    out = {}
+    for th in (0.0, 0.5, 2.0):
+        a = with_args(args, theta=th, steps=30, warmup=3)
+        res = run_gpu(a, "fp64")
+        rf, kernels, rfs = roofline(res, "fp64", th)
+        out[f"theta_{th}"] = {"value": round(res["value"], 1), "ms_per_step": round(res["ms_per_step"], 4),
+                              "roofline": rf}
+    return out
+
+
+def pure_gauge_links(dims, seed, sx=0.4, sy=0.3):
+    """Host-layout links of a cold configuration rotated by a random SL(3,C)
+    gauge transformation, U_mu(x) = O_x O_{x+mu}^-1 with O_x = exp(A_x),
+    A_x = i sum_a lambda_a (a + i b), a ~ N(0, sx), b ~ N(0, sy): gauge
+    equivalent to the identity, so cooling can bring d to 0."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    lam = np.zeros((8, 3, 3), complex)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1], lam[1][1, 0] = -1j, 1j
+    lam[2][0, 0], lam[2][1, 1] = 1, -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2], lam[4][2, 0] = -1j, 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2], lam[6][2, 1] = -1j, 1j
+    lam[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+    V = int(np.prod(dims))
+    c = rng.normal(0, sx, (V, 8)) + 1j * rng.normal(0, sy, (V, 8))
+    A = 1j * np.einsum("va,aij->vij", c, lam)
+
+    def expm(M):
+        # scaling and squaring of a 20-term Taylor series
+        k = max(0, int(np.ceil(np.log2(max(np.abs(M).sum(axis=(1, 2)).max(), 1e-300)))) + 1)
+        M = M / 2.0 ** k
+        E = np.broadcast_to(np.eye(3, dtype=complex), M.shape).copy()
+        T = E.copy()
+        for n in range(1, 21):
+            T = T @ M / n
+            E = E + T
+        for _ in range(k):
+            E = E @ E
+        return E
+
+    O = expm(A).reshape(dims[3], dims[2], dims[1], dims[0], 3, 3)
+    Oi = expm(-A).reshape(dims[3], dims[2], dims[1], dims[0], 3, 3)
+    U = np.zeros((dims[3], dims[2], dims[1], dims[0], 4, 3, 3), complex)
+    for mu in range(4):
+        U[..., mu, :, :] = O @ np.roll(Oi, -1, axis=3 - mu)
+    U = U.reshape(V, 4, 3, 3)
+    out = np.zeros((V, 4, 18))
+    out[..., 0::2] = U.real.reshape(V, 4, 9)
+    out[..., 1::2] = U.imag.reshape(V, 4, 9)
+    return out
+
+
+def cooling_modes(args):
+    """D_0 / D_1 / D_2 adaptive cooling of pure-gauge SL(3,C) starts at 16^4
+    (eps_c = 1e-2, alpha = 1): the distance d after every 50 cooling steps and
+    the time per cooling step, from a mild and a strong gauge rotation."""
+    import torch
+    import paper_1311_1056_amd as cl
+    dims = tuple(int(x) for x in args.dims.split(","))
+    out = {"start": "cold links under a random SL(3,C) gauge transformation exp(i lambda_a (a + i b))",
+           "eps_c": 1e-2, "alpha": 1.0}
+    for start, (sx, sy) in (("mild", (0.3, 0.15)), ("strong", (0.4, 0.3))):
+        U0 = pure_gauge_links(dims, 7, sx, sy)
+        rec = {"a_sigma": sx, "b_sigma": sy}
+        for name, mode in (("D0", cl.CL_ALPHA_FIXED), ("D1", cl.CL_ALPHA_UNORM), ("D2", cl.CL_ALPHA_GRAD)):
+            lat = cl.Lattice(dims, args.beta, 0.0, cl.CL_FP64, seed=7)
+            lat.set_links(U0)
+            d = [lat.unitarity_norm()]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status = "ok"
+            try:
+                for _ in range(4):
+                    lat.gauge_cool(50, 1e-2, 1.0, mode, sync=False)
+                    d.append(lat.unitarity_norm())
+            except cl.ClError as e:
+                status = "diverged" if e.status == cl.CL_ENONFINITE else f"error {e.status}"
+            dt = time.perf_counter() - t0
+            lat.close()
+            rec[name] = {"d_every_50_steps": [float(f"{x:.4e}") for x in d], "status": status,
+                         "ms_per_cooling_step": round(1e3 * dt / (50 * max(1, len(d) - 1)), 4)}
+        out[start] = rec
+    return out
+
+
+def alone_vs_batched(args, n=32):
+    """The first n runs of the served mix, all submitted at once to the server,
+    against the same runs one at a time through the lattice API."""
+    import torch
+    import paper_1311_1056_amd as cl
+    runs = served_mix(n)
+    srv = cl.Server(args.served_budget_mb << 20)
+    t0 = time.perf_counter()
+    for i, r in enumerate(runs):
+        srv.submit(r["dims"], r["beta"], r["theta"], r["prec"], r["seed"], r["n_steps"], r["eps0"], True,
+                   r["n_cool"], r["eps0"], 1.0, cl.CL_ALPHA_UNORM, tag=i)
+    res = []
+    while len(res) < n:
+        srv.step()
+        res += srv.poll()
+    tb = time.perf_counter() - t0
+    srv.close()
+    lu = sum(r["link_updates"] for r in res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in runs:
+        lat = cl.Lattice(r["dims"], r["beta"], r["theta"], r["prec"], r["seed"])
+        lat.init(True, 0.3, 0.05)
+        lat.run_steps(r["n_steps"], r["eps0"], True, r["n_cool"], r["eps0"], 1.0, cl.CL_ALPHA_UNORM)
+        lat.measure()
+        lat.close()
+    ta = time.perf_counter() - t0
+    return {"runs": n, "batched_link_updates_per_s": round(lu / tb, 1), "alone_link_updates_per_s": round(lu / ta, 1),
+            "batched_s": round(tb, 3), "alone_s": round(ta, 3)}
+
+
 def copy_calibration(mib):
     import torch
     n = mib * 1024 * 1024 // 4
@@ -269,6 +437,14 @@ def copy_calibration(mib):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}), flush=True)
+
+
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line is the only stdout)."""
+    print(f"bench.py [{time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -284,6 +460,7 @@ def main():
         return
     res = run_gpu(args, args.precision)
     rf, kernels, rfs = roofline(res, args.precision, args.theta)
+    progress(f"main workload: {res['value'] / 1e6:.1f} M link-updates/s")
     out = {
         "metric": METRIC,
         "value": round(res["value"], 1),
@@ -310,15 +487,28 @@ def main():
     }
     if args.precision == "fp64" and not args.no_mixed:
         mx = run_gpu(args, "mixed")
+        progress(f"mixed precision: {mx['value'] / 1e6:.1f} M link-updates/s")
         mrf, mk, mrfs = roofline(mx, "mixed", args.theta)
         out["mixed"] = {"value": round(mx["value"], 1), "ms_per_step": round(mx["ms_per_step"], 4),
                         "dtype": "f32 links/drift/cooling, f64 det renorm, reductions and control",
                         "roofline": mrf, "rooflines": mrfs}
+    if args.precision == "fp64" and not args.no_extra:
+        out["large_lattice"] = large_lattice(args)
+        progress("32^4 leg done")
+        out["theta_points"] = theta_points(args)
+        progress("theta points done")
+        out["cooling_modes"] = cooling_modes(args)
+        progress("cooling modes done")
     if args.served_runs > 0 and args.precision == "fp64":
         out["served"] = served(args, res["value"], args.served_runs, 0.7)
+        progress("served mix at 0.7x done")
         out["served_overload"] = served(args, res["value"], max(1, args.served_runs // 2), 1.5)
+        progress("served mix at 1.5x done")
+        out["served_alone_vs_batched"] = alone_vs_batched(args)
+        progress("alone vs batched done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

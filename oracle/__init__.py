@@ -75,6 +75,8 @@ def lib():
                               ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_int, dp]
         L.orc_run.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -279,6 +281,11 @@ def link_stats(dims, links):
 
 
 OBS_FIELDS = ("d_pre", "d_post", "plaq_re", "plaq_im", "q_re", "q_im", "eps", "kmax")
+
+
+def set_threads(n=0):
+    """Set (n > 0) and return the OpenMP thread count of the oracle (timing only)."""
+    return lib().orc_set_threads(int(n))
 
 
 def run(dims, links, beta, theta, seed, n_steps, eps0, adaptive, n_cool, eps_c, alpha=1.0,

@@ -30,6 +30,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 typedef double complex cplx;
 typedef struct { cplx a[3][3]; } M3;
@@ -146,7 +147,9 @@ static M3 m_exp(M3 A)
 {
     int k = 0;
     double nrm = m_norm1(A);
-    while (nrm > 0.5) { nrm *= 0.5; ++k; }
+    /* bounded: a finite double needs at most ~1025 halvings, and an infinite
+     * norm (a runaway) must not loop forever; its result is non-finite anyway */
+    while (nrm > 0.5 && k < 1100) { nrm *= 0.5; ++k; }
     A = m_scale(A, ldexp(1.0, -k));
     M3 sum = m_id(), term = m_id();
     for (int n = 1; n < 60; ++n) {
@@ -873,4 +876,12 @@ void orc_cl_noise_field(const int *dims, uint64_t seed, uint32_t step, double *e
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < g.V; ++s)
         for (int mu = 0; mu < 4; ++mu) orc_cl_noise(seed, s, mu, step, eta + (s * 4 + mu) * 8);
+}
+
+/* Thread count of the OpenMP loops (timing of the oracle only; results do not
+ * depend on it: every reduction runs serially in a fixed order). */
+int orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

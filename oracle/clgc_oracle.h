@@ -37,4 +37,7 @@ int orc_run(const int *dims, double *links, double beta, double theta_re, double
             uint32_t step0, int n_steps, double eps0, int adaptive, double drift_bound, double *bound,
             int n_cool, double eps_c, double alpha, int mode, double *obs);
 
+/* Set (n > 0) and return the OpenMP thread count; timing only. */
+int orc_set_threads(int n);
+
 #endif

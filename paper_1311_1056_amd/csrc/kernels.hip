@@ -111,6 +111,17 @@ __device__ __forceinline__ double gather_cool_all(const RunArgs& ra, double* lds
     return r;
 }
 
+// The run's status read once for the whole block and broadcast, so that every
+// wave of the block takes the same branch even if the word changes meanwhile.
+__device__ __forceinline__ bool block_run_ok(const Ctrl* cr)
+{
+    __shared__ int s_ok;
+    __syncthreads();  // the previous logical block of this workgroup may still read s_ok
+    if (threadIdx.x == 0) s_ok = cr->status == ST_OK;
+    __syncthreads();
+    return s_ok != 0;
+}
+
 // ---------------------------------------------------------------------------
 // logical-block iteration
 
@@ -623,7 +634,10 @@ __device__ __forceinline__ void herm_exp_pair(herm3<T> A, herm3<T>& E, herm3<T>&
                    T(2) * (norm2(A.u01) + norm2(A.u02) + norm2(A.u12));
     int k = 0;
     if (fro2 > T(1)) {
-        k = (int)ceil(T(0.5) * log2(fro2));
+        // a non-finite norm (a runaway) takes no squarings; its infinite log
+        // converted to int would give a loop of 2^31 squarings
+        const T lk = T(0.5) * log2(fro2);
+        k = lk < T(1100) ? (int)ceil(lk) : 0;
         const T sc = ldexp(T(1), -k);
         A.d0 *= sc;
         A.d1 *= sc;
@@ -779,8 +793,10 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
-    // block-uniform: this run still cools in this iteration
-    if (iter < ra.n_cool && cr->status == ST_OK) {
+    // this run still cools in this iteration; block 0 of this launch may flag
+    // the run non-finite while other blocks start, so one thread reads the
+    // status for its whole block (every wave takes the same branch)
+    if (iter < ra.n_cool && block_run_ok(cr)) {
         // unitarity norm entering the step: from the finalized update (step 0) or
         // reduced here from the previous step's apply partials (every block
         // reduces the same <= 512 values in the same order)

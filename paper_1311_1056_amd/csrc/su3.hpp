@@ -268,8 +268,11 @@ __device__ __forceinline__ mat3<R> m_exp_traceless(mat3<R> A)
     R fro2 = m_norm2(A);
     int k = 0;
     if (fro2 > R(1)) {
-        // smallest k with fro2 / 4^k <= 1
-        k = (int)ceil(R(0.5) * log2(fro2));
+        // smallest k with fro2 / 4^k <= 1; a non-finite norm (a runaway, flagged
+        // by the caller's reduction) takes no squarings: converting its infinite
+        // log to int would give a loop of 2^31 squarings
+        const R lk = R(0.5) * log2(fro2);
+        k = lk < R(1100) ? (int)ceil(lk) : 0;
         const R sc = ldexp(R(1), -k);
 #pragma unroll
         for (int i = 0; i < 3; ++i)

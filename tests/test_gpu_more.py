@@ -182,6 +182,31 @@ def test_errors(cl):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cooling_overflow_is_flagged_and_ends(cl, orc, prec):
+    """Fixed-alpha cooling with a large eps_c alpha on a strongly gauge-rotated
+    start overflows the links: the call must end promptly with CL_ENONFINITE
+    (regression: an infinite norm once turned the Hermitian exponential's
+    scaling count into 2^31 squarings), and the same start cools under D_1."""
+    dims = (4, 4, 4, 4)
+    U = orc.cold_links(dims)
+    orc.gauge_transform(dims, U, lu.random_sl3c(np.random.default_rng(5), 0.6, 0.4, n=lu.volume(dims)))
+    say("cooling overflow", dims, prec)
+    lat = cl.Lattice(dims, 6.0, 0.0, prec)
+    lat.set_links(U)
+    with pytest.raises(cl.ClError) as e:
+        for _ in range(10):
+            lat.gauge_cool(20, 0.5, 1.0, cl.CL_ALPHA_FIXED)
+    assert e.value.status == cl.CL_ENONFINITE
+    lat.close()
+    lat = cl.Lattice(dims, 6.0, 0.0, prec)
+    lat.set_links(U)
+    d0 = lat.unitarity_norm()
+    d = lat.gauge_cool(60, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    assert np.isfinite(d) and d < 1e-3 * d0
+    lat.close()
+
+
 def test_runaway_is_detected_and_not_advanced(cl, orc):
     """A non-finite link makes the drift non-finite: the step reports
     CL_ENONFINITE and leaves the links as they were."""

@@ -292,3 +292,18 @@ def test_sampled_drift_equals_full_drift(orc):
         K = orc.drift(dims, U, 5.0, theta).reshape(-1, 18)
         sel = np.arange(0, 4 * lu.volume(dims), 3)
         np.testing.assert_array_equal(orc.drift_links(dims, U, 5.0, theta, sel), K[sel])
+
+
+@pytest.mark.timeout(60)
+def test_expm_of_non_finite_matrix_terminates(orc):
+    """A runaway configuration can hand the exponential an infinite entry: the
+    scaling loop must stay bounded and the result be non-finite (regression:
+    halving an infinite norm never reached the threshold)."""
+    A = np.zeros((3, 3), complex)
+    A[0, 1] = np.inf
+    assert not np.all(np.isfinite(orc.expm(A)))
+    A[0, 1] = np.nan
+    assert not np.all(np.isfinite(orc.expm(A)))
+    # finite inputs of any size still give the exact exponential
+    X = 40.0 * lu.lie(np.random.default_rng(3).normal(size=8))
+    assert np.allclose(orc.expm(1j * X), scipy.linalg.expm(1j * X), rtol=1e-9, atol=1e-9)

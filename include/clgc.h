@@ -229,6 +229,84 @@ cl_status cl_server_stats_get(cl_server* srv, cl_server_stats* out);
 cl_status cl_server_destroy(cl_server* srv);
 
 /* Message for the last failing call on this thread ("" if none). */
+/* ------------------------------------------------------------------------
+ * SU(2) Polyakov chain (section "Adaptive gauge cooling in the SU(2) Polyakov
+ * chain model"): n_chains independent chains of n_links SL(2,C) links with
+ * S = -(beta/2) Tr(U_0 U_1 ... U_{n-1}), eq. (eq:s), beta complex, evolved by
+ * complex Langevin (Pauli generators, <eta_a eta_b> = 2 delta_ab, the update
+ * and det renormalisation of the SU(3) path) alternated with gauge cooling of
+ * eq. (eq:24) on the chain's sites (Omega_k = exp(-4 eps_c alpha_ad TL(G_k)),
+ * G_k = U_k U_k^dag - U_{k-1}^dag U_{k-1}, all sites from the same links) with
+ * the adaptive alpha_ad = alpha / D of the same section (D_0 = 1, D_1 = Tr UU^dag
+ * per link, D_2 = mean |f_ak|).  The model reduces to one link, so the exact
+ * equilibrium is <Tr P / 2> = I_2(beta) / I_1(beta).  FP64 only.
+ *
+ * Host (and device) link layout: links[((c * n_links + k) * 4 + 2 i + j) * 2 +
+ * {0: re, 1: im}], 8 doubles per link.  Noise: Philox4x32-10 with key = seed
+ * and counter (link k, CL step, chain c, tag 2 << 16 | draw), draws 0 and 1
+ * giving eta_1..eta_3; the start of cl_chain_init uses tag 3 (draws 0..3).
+ * ------------------------------------------------------------------------ */
+typedef struct cl_chain cl_chain;
+
+typedef struct {
+    int32_t n_links;     /* 1 .. 1024 */
+    int32_t n_chains;    /* >= 1 */
+    double beta_re, beta_im;
+    uint64_t seed;
+    int32_t obs_cap;     /* steps of per-step record kept on the device (may be 0) */
+} cl_chain_desc;
+
+/* one chain after the last call (see cl_chain_run for the sums) */
+typedef struct {
+    int64_t step;        /* CL steps done */
+    int32_t status;      /* 0, or 1 once a drift or norm was not finite (chain frozen) */
+    int32_t pad;
+    double L[2];         /* Polyakov loop Tr(U_0 ... U_{n-1}) / 2 */
+    double d;            /* (1/2n) sum_k Tr(U U^dag - 1), after cooling */
+    double d_pre;        /* the same before the cooling of the last step */
+    double eps, kmax;    /* of the last CL step */
+    double sum_L[2];     /* sums of L and d over the steps of the last cl_chain_run */
+    double sum_d;
+    double n_sum;        /* steps in those sums */
+} cl_chain_obs;
+
+/* Device bytes for the chains, their control blocks and obs_cap steps of record.
+ * CL_EINVAL: n_links outside 1..1024, n_chains < 1, obs_cap < 0, beta not finite. */
+cl_status cl_chain_bytes(const cl_chain_desc* desc, size_t* device_bytes);
+/* dev_buf: caller-owned, at least cl_chain_bytes, 256-byte aligned; the stream is
+ * the caller's.  The chains start at the identity (a cold start). */
+cl_status cl_chain_create(const cl_chain_desc* desc, void* dev_buf, size_t buf_bytes, void* hip_stream,
+                          cl_chain** out);
+cl_status cl_chain_destroy(cl_chain* ch);
+/* U_k = exp(i sigma_a (x_a + i y_a)), x_a ~ N(0, sigma_x), y_a ~ N(0, sigma_y);
+ * resets every control block (step 0, adaptive bound unset, status 0). */
+cl_status cl_chain_init(cl_chain* ch, double sigma_x, double sigma_y);
+/* host copies of all links (n_doubles = n_chains * n_links * 8); set_links
+ * resets the control blocks like cl_chain_init.  Synchronous. */
+cl_status cl_chain_set_links(cl_chain* ch, const double* host, size_t n_doubles);
+cl_status cl_chain_get_links(cl_chain* ch, double* host, size_t n_doubles);
+/* n_steps CL steps of every chain, each followed by cool->n_steps cooling
+ * steps (cool may be NULL: none) and a measurement, in one launch (one
+ * workgroup per chain; the links stay on chip between steps).  Adaptive step
+ * eps = min(eps0, B/K_max) per chain, B fixed on its first step (drift_bound if
+ * > 0).  record != 0 keeps (Re L, Im L, d, eps, kmax, d_pre) of every step in
+ * the device record (n_steps <= obs_cap), read with cl_chain_record.  A chain
+ * whose drift or norm turns non-finite keeps its last finite links and status
+ * 1.  Asynchronous on the stream.
+ * CL_EINVAL: n_steps < 0, record with n_steps > obs_cap, bad eps0/cooling. */
+cl_status cl_chain_run(cl_chain* ch, const cl_step_desc* step, const cl_cool_desc* cool, int n_steps, int record);
+/* cooling only: cool->n_steps steps of every chain (eq. (eq:24)), then L and d. */
+cl_status cl_chain_cool(cl_chain* ch, const cl_cool_desc* cool);
+/* the drift Khat_k = i beta TL(U_k ... U_{k-1}) of every link (host, same layout
+ * as the links) and, if kmax != NULL, K_max of every chain.  Synchronous;
+ * overwrites the device record. */
+cl_status cl_chain_drift(cl_chain* ch, double* host_K, size_t n_doubles, double* kmax);
+/* every chain's observables (cap >= n_chains); recomputes L and d from the
+ * current links.  Synchronous. */
+cl_status cl_chain_measure(cl_chain* ch, cl_chain_obs* out, int cap);
+/* the per-step record of the last recording cl_chain_run: n_steps x n_chains x 6. */
+cl_status cl_chain_record(cl_chain* ch, double* host, size_t n_doubles);
+
 const char* cl_last_error(void);
 
 #ifdef __cplusplus

@@ -1,4 +1,4 @@
-"""FP64 CPU oracle (ctypes wrapper around clgc_oracle.c).
+"""FP64 CPU oracle (ctypes wrapper around clgc_oracle.c and chain_oracle.c).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
 the benchmark's CPU-baseline leg.  The HIP library never imports it.
@@ -16,7 +16,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "clgc_oracle.c")
+_SRC = [os.path.join(_HERE, "clgc_oracle.c"), os.path.join(_HERE, "chain_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _lib = None
@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-             "-o", tmp, _SRC, "-lm"])
+             "-o", tmp, *_SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -77,6 +77,26 @@ def lib():
         L.orc_run.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = ctypes.c_int
+        # SU(2) Polyakov chain
+        c_u64, c_long, c_u32, c_int, c_d = ctypes.c_uint64, ctypes.c_long, ctypes.c_uint32, ctypes.c_int, ctypes.c_double
+        L.orc_chain_noise.argtypes = [c_u64, c_long, c_int, c_u32, dp]
+        L.orc_chain_init.argtypes = [c_int, c_long, c_u64, c_d, c_d, dp]
+        L.orc_chain_loop.argtypes = [c_int, dp, c_int, dp]
+        L.orc_chain_drift.argtypes = [c_int, dp, c_d, c_d, dp]
+        L.orc_chain_unorm.argtypes = [c_int, dp]
+        L.orc_chain_unorm.restype = c_d
+        L.orc_chain_measure.argtypes = [c_int, dp, c_d, c_d, dp]
+        L.orc_chain_update.argtypes = [c_int, dp, dp, c_d, c_u64, c_long, c_u32]
+        L.orc_chain_step.argtypes = [c_int, dp, c_d, c_d, c_u64, c_long, c_u32, c_d, c_int, c_d, dp, dp, dp]
+        L.orc_chain_step.restype = c_int
+        L.orc_chain_gradient.argtypes = [c_int, dp, dp]
+        L.orc_chain_cool_step.argtypes = [c_int, dp, c_d]
+        L.orc_chain_cool.argtypes = [c_int, dp, c_int, c_d, c_d, c_int, dp, dp]
+        L.orc_chain_cool.restype = c_int
+        L.orc_chain_run.argtypes = [c_int, dp, c_d, c_d, c_u64, c_long, c_u32, c_int, c_d, c_int, c_d, dp,
+                                    c_int, c_d, c_d, c_int, dp]
+        L.orc_chain_run.restype = c_int
+        L.orc_chain_expm.argtypes = [dp, dp]
         _lib = L
     return _lib
 
@@ -310,3 +330,124 @@ def cl_noise_field(dims, seed, step):
                                          ctypes.c_uint32, ctypes.POINTER(ctypes.c_double)]
     lib().orc_cl_noise_field(dp, seed, step, _dp(o))
     return o
+
+
+# ----------------------------------------------------------------------------
+# SU(2) Polyakov chain.  A chain is a float64 array (n, 8): link k as a 2x2
+# complex matrix, row-major, (re, im) interleaved; several chains are
+# (n_chains, n, 8).
+
+def chain_to_complex(links):
+    a = np.asarray(links, dtype=np.float64)
+    return (a[..., 0::2] + 1j * a[..., 1::2]).reshape(a.shape[:-1] + (2, 2))
+
+
+def chain_from_complex(m):
+    m = np.asarray(m, dtype=np.complex128)
+    out = np.zeros(m.shape[:-2] + (8,))
+    out[..., 0::2] = m.real.reshape(m.shape[:-2] + (4,))
+    out[..., 1::2] = m.imag.reshape(m.shape[:-2] + (4,))
+    return out
+
+
+def _chain(links):
+    a = np.ascontiguousarray(links, dtype=np.float64)
+    assert a.shape[-1] == 8
+    return a, a.shape[-2]
+
+
+def chain_noise(seed, chain, k, step):
+    o = np.zeros(3)
+    lib().orc_chain_noise(seed, chain, k, step, _dp(o))
+    return o
+
+
+def chain_init(n, chain, seed, sigma_x=0.3, sigma_y=0.05):
+    u = np.zeros((n, 8))
+    lib().orc_chain_init(n, chain, seed, sigma_x, sigma_y, _dp(u))
+    return u
+
+
+def chain_loop(links, k):
+    a, n = _chain(links)
+    o = np.zeros(8)
+    lib().orc_chain_loop(n, _dp(a), k, _dp(o))
+    return o
+
+
+def chain_drift(links, beta):
+    a, n = _chain(links)
+    b = complex(beta)
+    K = np.zeros((n, 8))
+    lib().orc_chain_drift(n, _dp(a), b.real, b.imag, _dp(K))
+    return K
+
+
+def chain_unorm(links):
+    a, n = _chain(links)
+    return lib().orc_chain_unorm(n, _dp(a))
+
+
+def chain_measure(links, beta):
+    """(L, d, S): Polyakov loop Tr(U_0...U_{n-1})/2, distance, action -beta L."""
+    a, n = _chain(links)
+    b = complex(beta)
+    o = np.zeros(5)
+    lib().orc_chain_measure(n, _dp(a), b.real, b.imag, _dp(o))
+    return complex(o[0], o[1]), o[2], complex(o[3], o[4])
+
+
+def chain_update(links, K, eps, seed, chain, step):
+    """In place on links."""
+    n = links.shape[-2]
+    lib().orc_chain_update(n, _dp(links), _dp(np.ascontiguousarray(K)), eps, seed, chain, step)
+
+
+def chain_step(links, beta, seed, chain, step, eps0, adaptive=False, drift_bound=0.0, bound=0.0):
+    """In place.  Returns (rc, eps, kmax, bound)."""
+    n = links.shape[-2]
+    b = complex(beta)
+    bd, e, k = np.array([bound]), np.zeros(1), np.zeros(1)
+    rc = lib().orc_chain_step(n, _dp(links), b.real, b.imag, seed, chain, step, eps0, int(adaptive), drift_bound,
+                              _dp(bd), _dp(e), _dp(k))
+    return rc, e[0], k[0], bd[0]
+
+
+def chain_gradient(links):
+    a, n = _chain(links)
+    f = np.zeros((n, 3))
+    lib().orc_chain_gradient(n, _dp(a), _dp(f))
+    return f
+
+
+def chain_cool_step(links, eps_alpha):
+    """In place: one Jacobi cooling step with eps * alpha_ad = eps_alpha."""
+    lib().orc_chain_cool_step(links.shape[-2], _dp(links), eps_alpha)
+
+
+def chain_cool(links, n_cool, eps_c, alpha=1.0, mode=0):
+    """In place.  Returns (rc, un[n_cool+1], alpha_used[n_cool])."""
+    n = links.shape[-2]
+    un, al = np.zeros(n_cool + 1), np.zeros(max(n_cool, 1))
+    rc = lib().orc_chain_cool(n, _dp(links), n_cool, eps_c, alpha, mode, _dp(un), _dp(al))
+    return rc, un, al[:n_cool]
+
+
+def chain_run(links, beta, seed, chain, n_steps, eps0, adaptive, n_cool, eps_c, alpha=1.0, mode=0,
+              step0=0, drift_bound=0.0, bound=0.0):
+    """In place.  Returns (rc, obs[n_steps, 6], bound); obs rows are
+    (Re L, Im L, d, eps, kmax, d before cooling)."""
+    n = links.shape[-2]
+    b = complex(beta)
+    bd = np.array([bound])
+    obs = np.zeros((n_steps, 6))
+    rc = lib().orc_chain_run(n, _dp(links), b.real, b.imag, seed, chain, step0, n_steps, eps0, int(adaptive),
+                             drift_bound, _dp(bd), n_cool, eps_c, alpha, mode, _dp(obs))
+    return rc, obs, bd[0]
+
+
+def chain_expm(A):
+    a = chain_from_complex(np.asarray(A, dtype=np.complex128).reshape(1, 2, 2))[0]
+    o = np.zeros(8)
+    lib().orc_chain_expm(_dp(np.ascontiguousarray(a)), _dp(o))
+    return chain_to_complex(o)

@@ -40,4 +40,25 @@ int orc_run(const int *dims, double *links, double beta, double theta_re, double
 /* Set (n > 0) and return the OpenMP thread count; timing only. */
 int orc_set_threads(int n);
 
+/* SU(2) Polyakov chain (chain_oracle.c); links: n x 8 doubles (2x2, row-major, re/im) */
+void orc_chain_noise(uint64_t seed, long chain, int k, uint32_t step, double eta[3]);
+void orc_chain_init(int n, long chain, uint64_t seed, double sx, double sy, double *links);
+void orc_chain_loop(int n, const double *links, int k, double out[8]);
+void orc_chain_drift(int n, const double *links, double beta_re, double beta_im, double *K);
+double orc_chain_unorm(int n, const double *links);
+void orc_chain_measure(int n, const double *links, double beta_re, double beta_im, double out[5]);
+void orc_chain_update(int n, double *links, const double *K, double eps, uint64_t seed, long chain,
+                      uint32_t step);
+int orc_chain_step(int n, double *links, double beta_re, double beta_im, uint64_t seed, long chain,
+                   uint32_t step, double eps0, int adaptive, double drift_bound, double *bound,
+                   double *eps_used, double *kmax_out);
+void orc_chain_gradient(int n, const double *links, double *f);
+void orc_chain_cool_step(int n, double *links, double eps_alpha);
+int orc_chain_cool(int n, double *links, int n_cool, double eps_c, double alpha, int mode, double *un,
+                   double *alpha_used);
+int orc_chain_run(int n, double *links, double beta_re, double beta_im, uint64_t seed, long chain,
+                  uint32_t step0, int n_steps, double eps0, int adaptive, double drift_bound, double *bound,
+                  int n_cool, double eps_c, double alpha, int mode, double *obs);
+void orc_chain_expm(const double *A, double *out);
+
 #endif

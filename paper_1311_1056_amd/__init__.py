@@ -68,6 +68,18 @@ class cl_server_stats(ctypes.Structure):
                 ("wait_s_p50", ctypes.c_double), ("wait_s_p99", ctypes.c_double)]
 
 
+class cl_chain_desc(ctypes.Structure):
+    _fields_ = [("n_links", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("beta_re", ctypes.c_double),
+                ("beta_im", ctypes.c_double), ("seed", ctypes.c_uint64), ("obs_cap", ctypes.c_int32)]
+
+
+class cl_chain_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("L", ctypes.c_double * 2), ("d", ctypes.c_double), ("d_pre", ctypes.c_double),
+                ("eps", ctypes.c_double), ("kmax", ctypes.c_double), ("sum_L", ctypes.c_double * 2),
+                ("sum_d", ctypes.c_double), ("n_sum", ctypes.c_double)]
+
+
 class ClError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"clgc error {status}: {msg}")
@@ -105,6 +117,17 @@ def _load():
         "cl_server_stats_get": [vp, P(cl_server_stats)],
         "cl_server_destroy": [vp],
         "cl_timing_read": [vp, dp, P(ctypes.c_int64), ctypes.c_int],
+        "cl_chain_bytes": [P(cl_chain_desc), P(sz)],
+        "cl_chain_create": [P(cl_chain_desc), vp, sz, vp, P(vp)],
+        "cl_chain_destroy": [vp],
+        "cl_chain_init": [vp, ctypes.c_double, ctypes.c_double],
+        "cl_chain_set_links": [vp, dp, sz],
+        "cl_chain_get_links": [vp, dp, sz],
+        "cl_chain_run": [vp, P(cl_step_desc), P(cl_cool_desc), ctypes.c_int, ctypes.c_int],
+        "cl_chain_cool": [vp, P(cl_cool_desc)],
+        "cl_chain_drift": [vp, dp, sz, dp],
+        "cl_chain_measure": [vp, P(cl_chain_obs), ctypes.c_int],
+        "cl_chain_record": [vp, dp, sz],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -328,3 +351,84 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Chain:
+    """n_chains SU(2) Polyakov chains of n_links links (complex beta), in a torch
+    device buffer, all work on one HIP stream.  Links are (n_chains, n_links, 8)
+    doubles: row-major 2x2 complex, (re, im) interleaved."""
+
+    def __init__(self, n_links, n_chains, beta, seed=0, obs_cap=0, device="cuda:0", stream=None):
+        import torch
+        b = complex(beta)
+        self.n_links, self.n_chains, self.beta = int(n_links), int(n_chains), b
+        self.desc = cl_chain_desc(self.n_links, self.n_chains, b.real, b.imag, int(seed), int(obs_cap))
+        nbytes = ctypes.c_size_t()
+        _check(lib.cl_chain_bytes(ctypes.byref(self.desc), ctypes.byref(nbytes)))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.buf.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p()
+        _check(lib.cl_chain_create(ctypes.byref(self.desc), ctypes.c_void_p(aligned), nbytes.value,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib.cl_chain_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, sigma_x=0.3, sigma_y=0.05):
+        _check(lib.cl_chain_init(self.handle, float(sigma_x), float(sigma_y)))
+
+    def set_links(self, links):
+        a = np.ascontiguousarray(np.asarray(links, dtype=np.float64).reshape(-1))
+        _check(lib.cl_chain_set_links(self.handle, _dp(a), a.size))
+
+    def get_links(self):
+        a = np.zeros(self.n_chains * self.n_links * 8)
+        _check(lib.cl_chain_get_links(self.handle, _dp(a), a.size))
+        return a.reshape(self.n_chains, self.n_links, 8)
+
+    def run(self, n_steps, eps0, adaptive=False, n_cool=0, eps_c=None, alpha=1.0, mode=CL_ALPHA_FIXED,
+            drift_bound=0.0, record=False):
+        sd = cl_step_desc(float(eps0), int(adaptive), float(drift_bound))
+        cd = cl_cool_desc(int(n_cool), float(eps0 if eps_c is None else eps_c), float(alpha), int(mode))
+        _check(lib.cl_chain_run(self.handle, ctypes.byref(sd), ctypes.byref(cd), int(n_steps), int(record)))
+
+    def cool(self, n_steps, eps_c, alpha=1.0, mode=CL_ALPHA_FIXED):
+        cd = cl_cool_desc(int(n_steps), float(eps_c), float(alpha), int(mode))
+        _check(lib.cl_chain_cool(self.handle, ctypes.byref(cd)))
+
+    def drift(self):
+        K = np.zeros(self.n_chains * self.n_links * 8)
+        km = np.zeros(self.n_chains)
+        _check(lib.cl_chain_drift(self.handle, _dp(K), K.size, _dp(km)))
+        return K.reshape(self.n_chains, self.n_links, 8), km
+
+    def measure(self):
+        """Per chain: dict of step, status, L, d, d_pre, eps, kmax, mean_L, mean_d (means over
+        the steps of the last run)."""
+        buf = (cl_chain_obs * self.n_chains)()
+        _check(lib.cl_chain_measure(self.handle, buf, self.n_chains))
+        out = []
+        for o in buf:
+            n = o.n_sum
+            out.append({"step": o.step, "status": o.status, "L": complex(o.L[0], o.L[1]), "d": o.d,
+                        "d_pre": o.d_pre, "eps": o.eps, "kmax": o.kmax, "n_sum": n,
+                        "mean_L": complex(o.sum_L[0], o.sum_L[1]) / n if n else complex("nan"),
+                        "mean_d": o.sum_d / n if n else float("nan")})
+        return out
+
+    def record(self, n_steps):
+        """(n_steps, n_chains, 6): Re L, Im L, d, eps, kmax, d before cooling."""
+        a = np.zeros(int(n_steps) * self.n_chains * 6)
+        _check(lib.cl_chain_record(self.handle, _dp(a), a.size))
+        return a.reshape(int(n_steps), self.n_chains, 6)

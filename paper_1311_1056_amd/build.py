@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libclgc.so")
-SOURCES = ["kernels.hip", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "server.cpp", "chain.hip", "chain_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -139,23 +139,24 @@ __device__ __forceinline__ m2 pick(bool p, const m2& x, const m2& y)
               {p ? x.c.re : y.c.re, p ? x.c.im : y.c.im}, {p ? x.d.re : y.d.re, p ? x.d.im : y.d.im}};
 }
 
-// LDS transfers element by element: a whole-struct copy between address
-// spaces becomes a memcpy that keeps the registers' copy in scratch memory
-__device__ __forceinline__ void put(m2& dst, const m2& x)
+// LDS transfers element by element into component-major arrays (a
+// whole-struct copy between address spaces would become a memcpy that keeps
+// the registers' copy in scratch memory)
+__device__ __forceinline__ void put(double (*arr)[kChainBlock], int i, const m2& x)
 {
-    dst.a.re = x.a.re;
-    dst.a.im = x.a.im;
-    dst.b.re = x.b.re;
-    dst.b.im = x.b.im;
-    dst.c.re = x.c.re;
-    dst.c.im = x.c.im;
-    dst.d.re = x.d.re;
-    dst.d.im = x.d.im;
+    arr[0][i] = x.a.re;
+    arr[1][i] = x.a.im;
+    arr[2][i] = x.b.re;
+    arr[3][i] = x.b.im;
+    arr[4][i] = x.c.re;
+    arr[5][i] = x.c.im;
+    arr[6][i] = x.d.re;
+    arr[7][i] = x.d.im;
 }
 
-__device__ __forceinline__ m2 get(const m2& x)
+__device__ __forceinline__ m2 get(const double (*arr)[kChainBlock], int i)
 {
-    return m2{{x.a.re, x.a.im}, {x.b.re, x.b.im}, {x.c.re, x.c.im}, {x.d.re, x.d.im}};
+    return m2{{arr[0][i], arr[1][i]}, {arr[2][i], arr[3][i]}, {arr[4][i], arr[5][i]}, {arr[6][i], arr[7][i]}};
 }
 
 // ---------------------------------------------------------------------------
@@ -192,10 +193,12 @@ __device__ __forceinline__ double block_all(double v, double* red)
 // ---------------------------------------------------------------------------
 // the per-chain workgroup state
 
+// Matrices in LDS are stored component-major (component e of thread t at
+// [e][t]), so that a wavefront's accesses fall on consecutive banks.
 struct ChainLds {
-    m2 pre[kChainBlock], suf[kChainBlock];  // scans / products
-    m2 edge[kChainBlock];                   // last link (or first Omega^-1) of every thread
-    m2 last;                                // link n-1
+    double pre[8][kChainBlock], suf[8][kChainBlock];  // scans / products
+    double edge[8][kChainBlock];  // last link, then the first Omega^-1, of every thread
+    double last[8];               // link n-1
     double red[kChainBlock / 64];
 };
 
@@ -216,21 +219,21 @@ __device__ __forceinline__ void chain_loops(const Chain& ch, ChainLds& s, m2 (&P
     // inclusive prefix I_t = M_0 ... M_t and suffix S_t = M_t ... M_last
     m2 I = M, S = M;
     for (int off = 1; off < kChainBlock; off <<= 1) {
-        put(s.pre[t], I);
-        put(s.suf[t], S);
+        put(s.pre, t, I);
+        put(s.suf, t, S);
         __syncthreads();
-        if (t >= off) I = mul(get(s.pre[t - off]), I);
-        if (t + off < kChainBlock) S = mul(S, get(s.suf[t + off]));
+        if (t >= off) I = mul(get(s.pre, t - off), I);
+        if (t + off < kChainBlock) S = mul(S, get(s.suf, t + off));
         __syncthreads();
     }
-    put(s.pre[t], I);
-    put(s.suf[t], S);
+    put(s.pre, t, I);
+    put(s.suf, t, S);
     __syncthreads();
     // (no ?: on matrix values below: it selects addresses and keeps the
     // operands in scratch memory)
     m2 E = m2_id(), F = m2_id();
-    if (t > 0) E = get(s.pre[t - 1]);                 // M_0 ... M_t-1
-    if (t + 1 < kChainBlock) F = get(s.suf[t + 1]);   // M_t+1 ... M_last
+    if (t > 0) E = get(s.pre, t - 1);                 // M_0 ... M_t-1
+    if (t + 1 < kChainBlock) F = get(s.suf, t + 1);   // M_t+1 ... M_last
     __syncthreads();
     // A_j = E U_0 ... U_j-1 (links before), B_j = U_j ... U_3 F (links from j on)
     m2 A[kChainPerThread], B[kChainPerThread];
@@ -253,13 +256,13 @@ __device__ __forceinline__ m2 chain_product(const Chain& ch, ChainLds& s)
 #pragma unroll
     for (int j = 0; j < kChainPerThread; ++j)
         if (ch.valid(j)) M = mul(M, ch.U[j]);
-    put(s.pre[t], M);
+    put(s.pre, t, M);
     __syncthreads();
     for (int off = 1; off < kChainBlock; off <<= 1) {
-        if ((t & (2 * off - 1)) == 0) put(s.pre[t], mul(get(s.pre[t]), get(s.pre[t + off])));
+        if ((t & (2 * off - 1)) == 0) put(s.pre, t, mul(get(s.pre, t), get(s.pre, t + off)));
         __syncthreads();
     }
-    const m2 r = get(s.pre[0]);
+    const m2 r = get(s.pre, 0);
     __syncthreads();
     return r;
 }
@@ -292,50 +295,113 @@ __device__ __forceinline__ double chain_drift(const ChainArgs& a, const Chain& c
     return sqrt(block_all<true>(kn2, s.red));
 }
 
+// Hermitian 2x2 [[p, q], [q*, r]] (p, r real)
+struct h2 {
+    double p, r;
+    cxd q;
+};
+
+// H U and U H for Hermitian H
+__device__ __forceinline__ m2 hmul(const h2& H, const m2& U)
+{
+    const cxd qc = conj(H.q);
+    return m2{cfma(H.q, U.c, H.p * U.a), cfma(H.q, U.d, H.p * U.b), cfma(qc, U.a, H.r * U.c), cfma(qc, U.b, H.r * U.d)};
+}
+
+__device__ __forceinline__ m2 mulh(const m2& U, const h2& H)
+{
+    const cxd qc = conj(H.q);
+    return m2{cfma(U.b, qc, H.p * U.a), cfma(U.b, cxd{H.r, 0.0}, U.a * H.q), cfma(U.d, qc, H.p * U.c),
+              cfma(U.d, cxd{H.r, 0.0}, U.c * H.q)};
+}
+
+// Omega = exp(A) and Omega^-1 = exp(-A) for A = [[g, q], [q*, -g]] Hermitian
+// traceless: A^2 = w 1 with w = g^2 + |q|^2 >= 0, so exp(+-A) = C 1 +- S A with
+// C = cosh(sqrt w), S = sinh(sqrt w) / sqrt w (exact inverses: C^2 - S^2 w = 1).
+__device__ __forceinline__ void herm_exp2(double g, cxd q, h2& Om, h2& Oi)
+{
+    const double w = fma(g, g, norm2(q));
+    double C, S;
+    if (w < 0.25) {
+        // even and odd series in w: the first omitted terms, w^10 / 20! and
+        // w^10 / 21!, are below 1e-24
+        C = 1.0;
+        S = 1.0;
+#pragma unroll
+        for (int m = 9; m >= 1; --m) {
+            C = fma(w * (1.0 / ((2.0 * m - 1.0) * (2.0 * m))), C, 1.0);
+            S = fma(w * (1.0 / ((2.0 * m) * (2.0 * m + 1.0))), S, 1.0);
+        }
+    } else {
+        const double l = sqrt(w), e = exp(l), ei = 1.0 / e;
+        C = 0.5 * (e + ei);
+        S = 0.5 * (e - ei) / l;
+    }
+    const double Sg = S * g;
+    const cxd Sq = {S * q.re, S * q.im};
+    Om = h2{C + Sg, C - Sg, Sq};
+    Oi = h2{C - Sg, C + Sg, cxd{-Sq.re, -Sq.im}};
+}
+
 // one Jacobi cooling step at eps_c alpha_ad chosen by the mode
 __device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, ChainLds& s)
 {
     const int t = threadIdx.x;
     // neighbours: link k-1 of this thread's first link
-    put(s.edge[t], ch.U[kChainPerThread - 1]);
+    put(s.edge, t, ch.U[kChainPerThread - 1]);
     if (ch.valid(0) && (ch.n - 1) / kChainPerThread == t) {
         // link n-1 by compile-time selects (a runtime index would put U in scratch)
         const int jl = (ch.n - 1) % kChainPerThread;
         m2 u = ch.U[0];
 #pragma unroll
         for (int j = 1; j < kChainPerThread; ++j) u = pick(j == jl, ch.U[j], u);
-        put(s.last, u);
+        s.last[0] = u.a.re;
+        s.last[1] = u.a.im;
+        s.last[2] = u.b.re;
+        s.last[3] = u.b.im;
+        s.last[4] = u.c.re;
+        s.last[5] = u.c.im;
+        s.last[6] = u.d.re;
+        s.last[7] = u.d.im;
     }
     __syncthreads();
-    m2 prev0 = get(s.last);
-    if (t > 0) prev0 = get(s.edge[t - 1]);
+    m2 prev0 = m2{{s.last[0], s.last[1]}, {s.last[2], s.last[3]}, {s.last[4], s.last[5]}, {s.last[6], s.last[7]}};
+    if (t > 0) prev0 = get(s.edge, t - 1);
     __syncthreads();
-    m2 G[kChainPerThread];
+    // G_k = TL(U U^dag - W^dag W) = [[g, q], [q*, -g]]: sum_a f_ak sigma_a = 4 TL(G_k)
+    // (the trace, the difference of the two links' norms, is no direction of the
+    // gauge orbit), f_1 = 4 Re q, f_2 = -4 Im q, f_3 = 4 g
+    double g[kChainPerThread];
+    cxd q[kChainPerThread];
     double un = 0.0, fsum = 0.0;
 #pragma unroll
     for (int j = 0; j < kChainPerThread; ++j) {
         m2 W = prev0;
         if (j > 0) W = ch.U[j - 1];
-        // sum_a f_ak sigma_a = 4 TL(G_k): the trace of U U^dag - W^dag W (the two
-        // links' norms differ) is no direction of the gauge orbit
-        G[j] = tl(sub(mul(ch.U[j], dag(ch.U[j])), mul(dag(W), W)));
+        const m2& U = ch.U[j];
+        const double h00 = norm2(U.a) + norm2(U.b) - norm2(W.a) - norm2(W.c);
+        const double h11 = norm2(U.c) + norm2(U.d) - norm2(W.b) - norm2(W.d);
+        // (U U^dag)_01 = a c* + b d*,  (W^dag W)_01 = wa* wb + wc* wd
+        const cxd uu = cfma(U.b, conj(U.d), U.a * conj(U.c));
+        const cxd ww = cfma(conj(W.c), W.d, conj(W.a) * W.b);
+        g[j] = 0.5 * (h00 - h11);
+        q[j] = uu - ww;
         if (ch.valid(j)) {
-            un += nrm2(ch.U[j]);
-            // |f_a| = |2 Tr(sigma_a G)|: 2|b + c|, 2|i (b - c)|, 2|a - d| (G Hermitian)
-            fsum += 2.0 * (fabs(G[j].b.re + G[j].c.re) + fabs(G[j].b.im - G[j].c.im) + fabs(G[j].a.re - G[j].d.re));
+            un += nrm2(U);
+            fsum += 4.0 * (fabs(q[j].re) + fabs(q[j].im) + fabs(g[j]));
         }
     }
     double D = 1.0;
     if (a.mode == 1) D = block_all<false>(un, s.red) / ch.n;
     if (a.mode == 2) D = block_all<false>(fsum, s.red) / (3.0 * ch.n);
     const double c = -4.0 * a.eps_c * (a.alpha / D);
-    m2 Om[kChainPerThread], Oi[kChainPerThread];
+    h2 Om[kChainPerThread], Oi[kChainPerThread];
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) {
-        Om[j] = exp_tl(scale(G[j], cxd{c, 0.0}));
-        Oi[j] = exp_tl(scale(G[j], cxd{-c, 0.0}));
-    }
-    put(s.edge[t], Oi[0]);
+    for (int j = 0; j < kChainPerThread; ++j) herm_exp2(c * g[j], cxd{c * q[j].re, c * q[j].im}, Om[j], Oi[j]);
+    s.edge[0][t] = Oi[0].p;
+    s.edge[1][t] = Oi[0].r;
+    s.edge[2][t] = Oi[0].q.re;
+    s.edge[3][t] = Oi[0].q.im;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kChainPerThread; ++j) {
@@ -343,11 +409,14 @@ __device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, C
         const int k = ch.k0 + j;
         // Omega^-1 of site k+1: this thread's next one, the next thread's first,
         // or (k = n-1) the first of the chain
-        m2 On;
-        if (k + 1 == ch.n) On = get(s.edge[0]);
-        else if (j + 1 < kChainPerThread) On = Oi[(j + 1) % kChainPerThread];
-        else On = get(s.edge[(t + 1) % kChainBlock]);
-        ch.U[j] = mul(mul(Om[j], ch.U[j]), On);
+        h2 On;
+        if (k + 1 == ch.n || j + 1 == kChainPerThread) {
+            const int o = k + 1 == ch.n ? 0 : (t + 1) % kChainBlock;
+            On = h2{s.edge[0][o], s.edge[1][o], cxd{s.edge[2][o], s.edge[3][o]}};
+        } else {
+            On = Oi[(j + 1) % kChainPerThread];
+        }
+        ch.U[j] = mulh(hmul(Om[j], ch.U[j]), On);
     }
     __syncthreads();
 }

@@ -2,14 +2,15 @@
 // Polyakov chain (section "Adaptive gauge cooling in the SU(2) Polyakov chain
 // model", action eq. (eq:s); cooling eq. (eq:24); distance eq. (d)).
 //
-// One workgroup owns one chain of n <= 1024 links for a whole call: four
-// links per thread live in registers, so a call of many CL steps reads and
-// writes HBM once.  Per CL step:
+// A chain of n <= 1024 links is owned by T threads of one workgroup for a
+// whole call (T the smallest power of two with 4 T >= n; short chains share a
+// workgroup): four links per thread live in registers, so a call of many CL
+// steps reads and writes HBM once.  Per CL step:
 //   drift   K_k = -D_a S sigma_a = i beta TL(P_k), P_k = U_k ... U_{n-1} U_0 ... U_{k-1}
 //           (the loop opened at link k), from an inclusive prefix and an
 //           inclusive suffix scan of the chain's 2x2 products in LDS
-//           (Hillis-Steele over the 256 per-thread products, 8 rounds);
-//   step    eps = min(eps0, B / K_max), K_max = max_k ||K_k|| (block max);
+//           (Hillis-Steele over the T per-thread products, log2 T rounds);
+//   step    eps = min(eps0, B / K_max), K_max = max_k ||K_k|| (chain max);
 //   update  U_k <- exp(i (eps K_k + sqrt(eps) eta_a sigma_a)) U_k, then
 //           U_k <- U_k / sqrt(det U_k);
 //   cooling n_c Jacobi steps: G_k = U_k U_k^dag - U_{k-1}^dag U_{k-1},
@@ -17,8 +18,8 @@
 //           for f_ak = 2 Tr(sigma_a G_k)), U_k <- Omega_k U_k Omega_{k+1}^{-1};
 //           alpha_ad = alpha / D with D_0 = 1, D_1 = UN / n, D_2 = mean |f_ak|;
 //   measure L = Tr(U_0 ... U_{n-1}) / 2 (ordered tree product), d = UN/(2n) - 1.
-// All block reductions are fixed-order, so a chain's result does not depend
-// on the launch.  Exponentials of traceless 2x2 matrices use X^2 = w 1:
+// All reductions over a chain are fixed-order, so a chain's result does not
+// depend on the launch or the other chains.  Exponentials of traceless 2x2 matrices use X^2 = w 1:
 // exp(X) = C(w) 1 + S(w) X with the even and odd series C, S in w.
 #include "chain.hpp"
 #include "philox.hpp"
@@ -139,10 +140,12 @@ __device__ __forceinline__ m2 pick(bool p, const m2& x, const m2& y)
               {p ? x.c.re : y.c.re, p ? x.c.im : y.c.im}, {p ? x.d.re : y.d.re, p ? x.d.im : y.d.im}};
 }
 
-// LDS transfers element by element into component-major arrays (a
-// whole-struct copy between address spaces would become a memcpy that keeps
-// the registers' copy in scratch memory)
-__device__ __forceinline__ void put(double (*arr)[kChainBlock], int i, const m2& x)
+// LDS transfers element by element into component-major arrays (component e
+// of slot i at [e][i], so that a wavefront's accesses fall on consecutive
+// banks; a whole-struct copy between address spaces would become a memcpy
+// that keeps the registers' copy in scratch memory)
+template <int B>
+__device__ __forceinline__ void put(double (*arr)[B], int i, const m2& x)
 {
     arr[0][i] = x.a.re;
     arr[1][i] = x.a.im;
@@ -154,53 +157,41 @@ __device__ __forceinline__ void put(double (*arr)[kChainBlock], int i, const m2&
     arr[7][i] = x.d.im;
 }
 
-__device__ __forceinline__ m2 get(const double (*arr)[kChainBlock], int i)
+template <int B>
+__device__ __forceinline__ m2 get(const double (*arr)[B], int i)
 {
     return m2{{arr[0][i], arr[1][i]}, {arr[2][i], arr[3][i]}, {arr[4][i], arr[5][i]}, {arr[6][i], arr[7][i]}};
 }
 
 // ---------------------------------------------------------------------------
-// block reductions (fixed order: waves in order, lanes by butterfly)
+// workgroup layout: a chain of n links is owned by T threads (the smallest
+// power of two with kChainPerThread T >= n), four consecutive links each; a
+// workgroup of B threads (64 for T <= 64, else 256) holds B / T chains.
 
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ double wave_max_d(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-template <bool MAX>
-__device__ __forceinline__ double block_all(double v, double* red)
-{
-    v = MAX ? wave_max_d(v) : wave_sum_d(v);
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[wv] = v;
-    __syncthreads();
-    double r = red[0];
-#pragma unroll
-    for (int i = 1; i < kChainBlock / 64; ++i) r = MAX ? fmax(r, red[i]) : r + red[i];
-    __syncthreads();
-    return r;
-}
-
-// ---------------------------------------------------------------------------
-// the per-chain workgroup state
-
-// Matrices in LDS are stored component-major (component e of thread t at
-// [e][t]), so that a wavefront's accesses fall on consecutive banks.
+template <int B>
 struct ChainLds {
-    double pre[8][kChainBlock], suf[8][kChainBlock];  // scans / products
-    double edge[8][kChainBlock];  // last link, then the first Omega^-1, of every thread
-    double last[8];               // link n-1
-    double red[kChainBlock / 64];
+    double pre[8][B], suf[8][B];  // scans / products; suf[.][first] also holds link n-1
+    double edge[8][B];            // last link, then the first Omega, of every thread
+    double red[B / 64];
+    int dead[B / 64];
 };
+
+struct Seg {
+    int t;      // thread in the workgroup
+    int lt;     // thread in the chain
+    int T;      // threads per chain
+    int first;  // the chain's first thread in the workgroup
+};
+
+__device__ __forceinline__ Seg make_seg(int T)
+{
+    Seg g;
+    g.t = (int)threadIdx.x;
+    g.T = T;
+    g.lt = g.t & (T - 1);
+    g.first = g.t - g.lt;
+    return g;
+}
 
 struct Chain {
     m2 U[kChainPerThread];
@@ -208,79 +199,135 @@ struct Chain {
     __device__ bool valid(int j) const { return k0 + j < n; }
 };
 
-// The loops P_k of this thread's links (drift) and the chain's product.
-__device__ __forceinline__ void chain_loops(const Chain& ch, ChainLds& s, m2 (&P)[kChainPerThread])
+// ---------------------------------------------------------------------------
+// reductions over one chain's threads, in a fixed order (a butterfly within
+// the wavefront, then the chain's wavefronts in order), so that a chain's
+// result depends on n only; every thread of the chain gets the same value.
+
+template <bool MAX, int B>
+__device__ __forceinline__ double chain_all(double v, const Seg& g, ChainLds<B>& s)
 {
-    const int t = threadIdx.x;
-    m2 M = m2_id();
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j)
-        if (ch.valid(j)) M = mul(M, ch.U[j]);
-    // inclusive prefix I_t = M_0 ... M_t and suffix S_t = M_t ... M_last
-    m2 I = M, S = M;
-    for (int off = 1; off < kChainBlock; off <<= 1) {
-        put(s.pre, t, I);
-        put(s.suf, t, S);
-        __syncthreads();
-        if (t >= off) I = mul(get(s.pre, t - off), I);
-        if (t + off < kChainBlock) S = mul(S, get(s.suf, t + off));
-        __syncthreads();
+    for (int off = 32; off >= 1; off >>= 1) {
+        if (off < g.T) {
+            const double o = __shfl_xor(v, off, 64);
+            v = MAX ? fmax(v, o) : v + o;
+        }
     }
-    put(s.pre, t, I);
-    put(s.suf, t, S);
-    __syncthreads();
-    // (no ?: on matrix values below: it selects addresses and keeps the
-    // operands in scratch memory)
-    m2 E = m2_id(), F = m2_id();
-    if (t > 0) E = get(s.pre, t - 1);                 // M_0 ... M_t-1
-    if (t + 1 < kChainBlock) F = get(s.suf, t + 1);   // M_t+1 ... M_last
-    __syncthreads();
-    // A_j = E U_0 ... U_j-1 (links before), B_j = U_j ... U_3 F (links from j on)
-    m2 A[kChainPerThread], B[kChainPerThread];
-    // (invalid links are the identity, so they need no test)
-    A[0] = E;
+    if (B > 64 && g.T > 64) {
+        if ((g.t & 63) == 0) s.red[g.t >> 6] = v;
+        __syncthreads();
+        const int w0 = g.first >> 6;
+        double r = s.red[w0];
 #pragma unroll
-    for (int j = 1; j < kChainPerThread; ++j) A[j] = mul(A[j - 1], ch.U[j - 1]);
-    B[kChainPerThread - 1] = mul(ch.U[kChainPerThread - 1], F);
-#pragma unroll
-    for (int j = kChainPerThread - 2; j >= 0; --j) B[j] = mul(ch.U[j], B[j + 1]);
-#pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) P[j] = mul(B[j], A[j]);
+        for (int i = 1; i < (g.T >> 6); ++i) r = MAX ? fmax(r, s.red[w0 + i]) : r + s.red[w0 + i];
+        __syncthreads();
+        v = r;
+    }
+    return v;
 }
 
-// ordered product U_0 ... U_{n-1} (valid in every thread)
-__device__ __forceinline__ m2 chain_product(const Chain& ch, ChainLds& s)
+// true in every thread when p holds in every thread of the workgroup
+template <int B>
+__device__ __forceinline__ bool block_all_true(bool p, ChainLds<B>& s)
 {
-    const int t = threadIdx.x;
-    m2 M = m2_id();
-#pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j)
-        if (ch.valid(j)) M = mul(M, ch.U[j]);
-    put(s.pre, t, M);
+    const bool w = __all(p);
+    if (B == 64) return w;
+    if ((threadIdx.x & 63) == 0) s.dead[threadIdx.x >> 6] = w;
     __syncthreads();
-    for (int off = 1; off < kChainBlock; off <<= 1) {
-        if ((t & (2 * off - 1)) == 0) put(s.pre, t, mul(get(s.pre, t), get(s.pre, t + off)));
-        __syncthreads();
-    }
-    const m2 r = get(s.pre, 0);
+    bool r = true;
+#pragma unroll
+    for (int i = 0; i < B / 64; ++i) r = r && s.dead[i];
     __syncthreads();
     return r;
 }
 
-__device__ __forceinline__ double chain_unorm(const Chain& ch, ChainLds& s)
+// E = M_0 ... M_t-1 and F = M_t+1 ... M_T-1, the chain's products before and
+// after this thread's links (M_t = U_k0 ... U_k0+3), from an inclusive prefix
+// and an inclusive suffix scan over the chain's threads (Hillis-Steele)
+template <int B>
+__device__ __forceinline__ void chain_ends(const Chain& ch, const Seg& g, ChainLds<B>& s, m2& E, m2& F)
+{
+    m2 M = m2_id();
+#pragma unroll
+    for (int j = 0; j < kChainPerThread; ++j)
+        if (ch.valid(j)) M = mul(M, ch.U[j]);
+    m2 I = M, S = M;
+#pragma unroll
+    for (int off = 1; off < g.T; off <<= 1) {
+        put(s.pre, g.t, I);
+        put(s.suf, g.t, S);
+        __syncthreads();
+        if (g.lt >= off) I = mul(get(s.pre, g.t - off), I);
+        if (g.lt + off < g.T) S = mul(S, get(s.suf, g.t + off));
+        __syncthreads();
+    }
+    put(s.pre, g.t, I);
+    put(s.suf, g.t, S);
+    __syncthreads();
+    // (no ?: on matrix values: it selects addresses and keeps the operands in
+    // scratch memory)
+    E = m2_id();
+    F = m2_id();
+    if (g.lt > 0) E = get(s.pre, g.t - 1);
+    if (g.lt + 1 < g.T) F = get(s.suf, g.t + 1);
+    __syncthreads();
+}
+
+// The loop opened at each of this thread's links, P_j = U_j ... U_3 F E U_0 ...
+// U_j-1 (invalid links are the identity and need no test): with A_j = E U_0 ...
+// U_j-1 and B_j = U_j ... U_3 F, P_j = B_j A_j.
+__device__ __forceinline__ void chain_loops(const Chain& ch, const m2& E, const m2& F, m2 (&P)[kChainPerThread])
+{
+    m2 A[kChainPerThread], Bm[kChainPerThread];
+    A[0] = E;
+#pragma unroll
+    for (int j = 1; j < kChainPerThread; ++j) A[j] = mul(A[j - 1], ch.U[j - 1]);
+    Bm[kChainPerThread - 1] = mul(ch.U[kChainPerThread - 1], F);
+#pragma unroll
+    for (int j = kChainPerThread - 2; j >= 0; --j) Bm[j] = mul(ch.U[j], Bm[j + 1]);
+#pragma unroll
+    for (int j = 0; j < kChainPerThread; ++j) P[j] = mul(Bm[j], A[j]);
+}
+
+// ordered product U_0 ... U_{n-1} (valid in every thread of the chain)
+template <int B>
+__device__ __forceinline__ m2 chain_product(const Chain& ch, const Seg& g, ChainLds<B>& s)
+{
+    m2 M = m2_id();
+#pragma unroll
+    for (int j = 0; j < kChainPerThread; ++j)
+        if (ch.valid(j)) M = mul(M, ch.U[j]);
+    put(s.pre, g.t, M);
+    __syncthreads();
+#pragma unroll
+    for (int off = 1; off < g.T; off <<= 1) {
+        if ((g.lt & (2 * off - 1)) == 0) put(s.pre, g.t, mul(get(s.pre, g.t), get(s.pre, g.t + off)));
+        __syncthreads();
+    }
+    const m2 r = get(s.pre, g.first);
+    __syncthreads();
+    return r;
+}
+
+template <int B>
+__device__ __forceinline__ double chain_unorm(const Chain& ch, const Seg& g, ChainLds<B>& s)
 {
     double u = 0.0;
 #pragma unroll
     for (int j = 0; j < kChainPerThread; ++j)
         if (ch.valid(j)) u += nrm2(ch.U[j]);
-    return block_all<false>(u, s.red);
+    return chain_all<false>(u, g, s);
 }
 
-// the drift of this thread's links and K_max of the chain
-__device__ __forceinline__ double chain_drift(const ChainArgs& a, const Chain& ch, ChainLds& s,
+// the drift K_j = i beta TL(P_j) of this thread's links and K_max of the chain
+template <int B>
+__device__ __forceinline__ double chain_drift(const ChainArgs& a, const Chain& ch, const Seg& g, ChainLds<B>& s,
                                               m2 (&K)[kChainPerThread])
 {
-    chain_loops(ch, s, K);
+    m2 E, F;
+    chain_ends(ch, g, s, E, F);
+    chain_loops(ch, E, F, K);
     const cxd ib = {-a.beta_im, a.beta_re};  // i beta
     double kn2 = 0.0;
 #pragma unroll
@@ -292,7 +339,7 @@ __device__ __forceinline__ double chain_drift(const ChainArgs& a, const Chain& c
             kn2 = fmax(kn2, v);
         }
     }
-    return sqrt(block_all<true>(kn2, s.red));
+    return sqrt(chain_all<true>(kn2, g, s));
 }
 
 // Hermitian 2x2 [[p, q], [q*, r]] (p, r real)
@@ -315,10 +362,18 @@ __device__ __forceinline__ m2 mulh(const m2& U, const h2& H)
               cfma(U.d, cxd{H.r, 0.0}, U.c * H.q)};
 }
 
-// Omega = exp(A) and Omega^-1 = exp(-A) for A = [[g, q], [q*, -g]] Hermitian
-// traceless: A^2 = w 1 with w = g^2 + |q|^2 >= 0, so exp(+-A) = C 1 +- S A with
+// Omega = exp(A) = C 1 + S A and Omega^-1 = exp(-A) = C 1 - S A for
+// A = [[g, q], [q*, -g]] Hermitian traceless: A^2 = w 1 with w = g^2 + |q|^2 >= 0,
 // C = cosh(sqrt w), S = sinh(sqrt w) / sqrt w (exact inverses: C^2 - S^2 w = 1).
-__device__ __forceinline__ void herm_exp2(double g, cxd q, h2& Om, h2& Oi)
+// Both are kept as (C, S g, S q).
+struct hexp {
+    double C, Sg;
+    cxd Sq;
+    __device__ h2 fwd() const { return h2{C + Sg, C - Sg, Sq}; }
+    __device__ h2 inv() const { return h2{C - Sg, C + Sg, cxd{-Sq.re, -Sq.im}}; }
+};
+
+__device__ __forceinline__ hexp herm_exp2(double g, cxd q)
 {
     const double w = fma(g, g, norm2(q));
     double C, S;
@@ -337,41 +392,31 @@ __device__ __forceinline__ void herm_exp2(double g, cxd q, h2& Om, h2& Oi)
         C = 0.5 * (e + ei);
         S = 0.5 * (e - ei) / l;
     }
-    const double Sg = S * g;
-    const cxd Sq = {S * q.re, S * q.im};
-    Om = h2{C + Sg, C - Sg, Sq};
-    Oi = h2{C - Sg, C + Sg, cxd{-Sq.re, -Sq.im}};
+    return hexp{C, S * g, cxd{S * q.re, S * q.im}};
 }
 
 // one Jacobi cooling step at eps_c alpha_ad chosen by the mode
-__device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, ChainLds& s)
+template <int B>
+__device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, const Seg& g, ChainLds<B>& s)
 {
-    const int t = threadIdx.x;
-    // neighbours: link k-1 of this thread's first link
-    put(s.edge, t, ch.U[kChainPerThread - 1]);
-    if (ch.valid(0) && (ch.n - 1) / kChainPerThread == t) {
+    // neighbours: link k-1 of this thread's first link (link n-1 for k = 0)
+    put(s.edge, g.t, ch.U[kChainPerThread - 1]);
+    if (ch.valid(0) && (ch.n - 1) / kChainPerThread == g.lt) {
         // link n-1 by compile-time selects (a runtime index would put U in scratch)
         const int jl = (ch.n - 1) % kChainPerThread;
         m2 u = ch.U[0];
 #pragma unroll
         for (int j = 1; j < kChainPerThread; ++j) u = pick(j == jl, ch.U[j], u);
-        s.last[0] = u.a.re;
-        s.last[1] = u.a.im;
-        s.last[2] = u.b.re;
-        s.last[3] = u.b.im;
-        s.last[4] = u.c.re;
-        s.last[5] = u.c.im;
-        s.last[6] = u.d.re;
-        s.last[7] = u.d.im;
+        put(s.suf, g.first, u);
     }
     __syncthreads();
-    m2 prev0 = m2{{s.last[0], s.last[1]}, {s.last[2], s.last[3]}, {s.last[4], s.last[5]}, {s.last[6], s.last[7]}};
-    if (t > 0) prev0 = get(s.edge, t - 1);
+    m2 prev0 = get(s.suf, g.first);
+    if (g.lt > 0) prev0 = get(s.edge, g.t - 1);
     __syncthreads();
     // G_k = TL(U U^dag - W^dag W) = [[g, q], [q*, -g]]: sum_a f_ak sigma_a = 4 TL(G_k)
     // (the trace, the difference of the two links' norms, is no direction of the
     // gauge orbit), f_1 = 4 Re q, f_2 = -4 Im q, f_3 = 4 g
-    double g[kChainPerThread];
+    double gd[kChainPerThread];
     cxd q[kChainPerThread];
     double un = 0.0, fsum = 0.0;
 #pragma unroll
@@ -384,52 +429,55 @@ __device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, C
         // (U U^dag)_01 = a c* + b d*,  (W^dag W)_01 = wa* wb + wc* wd
         const cxd uu = cfma(U.b, conj(U.d), U.a * conj(U.c));
         const cxd ww = cfma(conj(W.c), W.d, conj(W.a) * W.b);
-        g[j] = 0.5 * (h00 - h11);
+        gd[j] = 0.5 * (h00 - h11);
         q[j] = uu - ww;
         if (ch.valid(j)) {
             un += nrm2(U);
-            fsum += 4.0 * (fabs(q[j].re) + fabs(q[j].im) + fabs(g[j]));
+            fsum += 4.0 * (fabs(q[j].re) + fabs(q[j].im) + fabs(gd[j]));
         }
     }
     double D = 1.0;
-    if (a.mode == 1) D = block_all<false>(un, s.red) / ch.n;
-    if (a.mode == 2) D = block_all<false>(fsum, s.red) / (3.0 * ch.n);
+    if (a.mode == 1) D = chain_all<false>(un, g, s) / ch.n;
+    if (a.mode == 2) D = chain_all<false>(fsum, g, s) / (3.0 * ch.n);
     const double c = -4.0 * a.eps_c * (a.alpha / D);
-    h2 Om[kChainPerThread], Oi[kChainPerThread];
+    hexp Om[kChainPerThread];
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) herm_exp2(c * g[j], cxd{c * q[j].re, c * q[j].im}, Om[j], Oi[j]);
-    s.edge[0][t] = Oi[0].p;
-    s.edge[1][t] = Oi[0].r;
-    s.edge[2][t] = Oi[0].q.re;
-    s.edge[3][t] = Oi[0].q.im;
+    for (int j = 0; j < kChainPerThread; ++j) Om[j] = herm_exp2(c * gd[j], cxd{c * q[j].re, c * q[j].im});
+    s.edge[0][g.t] = Om[0].C;
+    s.edge[1][g.t] = Om[0].Sg;
+    s.edge[2][g.t] = Om[0].Sq.re;
+    s.edge[3][g.t] = Om[0].Sq.im;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kChainPerThread; ++j) {
         if (!ch.valid(j)) continue;
         const int k = ch.k0 + j;
-        // Omega^-1 of site k+1: this thread's next one, the next thread's first,
-        // or (k = n-1) the first of the chain
-        h2 On;
+        // Omega^-1 of site k+1: this thread's next one, the next thread's first
+        // (always of the same chain: the chain's last thread holds link n-1),
+        // or, for k = n-1, the chain's first
+        hexp On;
         if (k + 1 == ch.n || j + 1 == kChainPerThread) {
-            const int o = k + 1 == ch.n ? 0 : (t + 1) % kChainBlock;
-            On = h2{s.edge[0][o], s.edge[1][o], cxd{s.edge[2][o], s.edge[3][o]}};
+            const int o = k + 1 == ch.n ? g.first : g.t + 1;
+            On = hexp{s.edge[0][o], s.edge[1][o], cxd{s.edge[2][o], s.edge[3][o]}};
         } else {
-            On = Oi[(j + 1) % kChainPerThread];
+            On = Om[(j + 1) % kChainPerThread];
         }
-        ch.U[j] = mulh(hmul(Om[j], ch.U[j]), On);
+        ch.U[j] = mulh(hmul(Om[j].fwd(), ch.U[j]), On.inv());
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ void chain_load(const ChainArgs& a, int chain, Chain& ch)
+// this thread's links of a chain; a chain index past the last (the padding
+// of the last workgroup) gets identity links and is never stored
+__device__ __forceinline__ void chain_load(const ChainArgs& a, int chain, const Seg& g, Chain& ch)
 {
     ch.n = a.n;
-    ch.k0 = (int)threadIdx.x * kChainPerThread;
+    ch.k0 = g.lt * kChainPerThread;
     const double* base = a.links + (size_t)chain * a.n * 8;
 #pragma unroll
     for (int j = 0; j < kChainPerThread; ++j) {
         ch.U[j] = m2_id();
-        if (ch.valid(j)) ch.U[j] = load_link(base + (size_t)(ch.k0 + j) * 8);
+        if (chain < a.n_chains && ch.valid(j)) ch.U[j] = load_link(base + (size_t)(ch.k0 + j) * 8);
     }
 }
 
@@ -441,14 +489,16 @@ __device__ __forceinline__ void chain_store(const ChainArgs& a, int chain, const
         if (ch.valid(j)) store_link(base + (size_t)(ch.k0 + j) * 8, ch.U[j]);
 }
 
+__device__ __forceinline__ int chain_of(const Seg& g, int B) { return (int)blockIdx.x * (B / g.T) + g.t / g.T; }
+
 // ---------------------------------------------------------------------------
 // kernels
 
 // U_k = exp(i sigma_a (x_a + i y_a)), x ~ N(0, sx), y ~ N(0, sy); fresh control block
-__global__ void __launch_bounds__(kChainBlock) k_chain_init(ChainArgs a, double sx, double sy)
+__global__ void __launch_bounds__(256) k_chain_init(ChainArgs a, double sx, double sy)
 {
     const int chain = blockIdx.y;
-    const int k = blockIdx.x * kChainBlock + (int)threadIdx.x;
+    const int k = blockIdx.x * 256 + (int)threadIdx.x;
     if (k < a.n) {
         double p[8];
 #pragma unroll
@@ -469,41 +519,41 @@ __global__ void __launch_bounds__(kChainBlock) k_chain_init(ChainArgs a, double 
 
 // n_steps CL steps of every chain, each followed by n_cool cooling steps and a
 // measurement; the record of step i of chain c goes to obs[i][c] if asked.
-__global__ void __launch_bounds__(kChainBlock) k_chain_run(ChainArgs a, int n_steps)
+// A chain that runs away (a non-finite drift maximum, norm or loop) keeps its
+// links of the call's start and is advanced no further; its workgroup goes on
+// (every thread takes every barrier) until all of its chains are done.
+template <int B, int T>
+__global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
 {
-    __shared__ ChainLds s;
-    const int chain = blockIdx.x;
+    __shared__ ChainLds<B> s;
+    const Seg g = make_seg(T);
+    const int chain = chain_of(g, B);
+    const bool exists = chain < a.n_chains;
     ChainCtrl* cc = a.ctrl + chain;
-    __shared__ int s_status;
-    __shared__ int64_t s_step;
-    __shared__ double s_bound;
-    if (threadIdx.x == 0) {
-        s_status = cc->status;
-        s_step = cc->step;
-        s_bound = cc->bound;
-    }
-    __syncthreads();
-    if (s_status != 0) return;  // block-uniform
-    int64_t step = s_step;
-    double bound = s_bound;
+    // (every thread of a chain reads the same words)
+    int status = exists ? cc->status : 1;
+    if (block_all_true(status != 0, s)) return;  // workgroup-uniform
+    int64_t step = exists ? cc->step : 0;
+    double bound = exists ? cc->bound : 0.0;
     Chain ch;
-    chain_load(a, chain, ch);
+    chain_load(a, chain, g, ch);
     double sL_re = 0.0, sL_im = 0.0, sd = 0.0, eps = 0.0, kmax = 0.0, d_pre = 0.0, d = 0.0;
     cxd L = {0.0, 0.0};
-    int status = 0, done = 0;
+    int done = 0;
     for (int i = 0; i < n_steps; ++i) {
         m2 K[kChainPerThread];
-        kmax = chain_drift(a, ch, s, K);
-        if (!isfinite(kmax)) {  // block-uniform (a block maximum)
-            status = 1;
-            break;
+        const double km = chain_drift(a, ch, g, s, K);  // chain-uniform
+        if (status == 0) {
+            kmax = km;
+            if (!isfinite(km)) status = 1;
         }
-        eps = a.eps0;
+        const bool live = status == 0;  // this step advances the chain
+        double e = a.eps0;
         if (a.adaptive) {
-            if (bound <= 0.0) bound = a.drift_bound > 0.0 ? a.drift_bound : a.eps0 * kmax;
-            if (kmax > 0.0 && bound / kmax < a.eps0) eps = bound / kmax;
+            if (live && bound <= 0.0) bound = a.drift_bound > 0.0 ? a.drift_bound : a.eps0 * km;
+            if (km > 0.0 && bound / km < a.eps0) e = bound / km;
         }
-        const double se = sqrt(eps) * 1.41421356237309504880;  // sqrt(eps) * sqrt(2)
+        const double se = sqrt(e) * 1.41421356237309504880;  // sqrt(eps) * sqrt(2)
 #pragma unroll
         for (int j = 0; j < kChainPerThread; ++j) {
             if (!ch.valid(j)) continue;
@@ -513,40 +563,46 @@ __global__ void __launch_bounds__(kChainBlock) k_chain_run(ChainArgs a, int n_st
             normal_pair<double>(a.seed, k, (uint32_t)step, (uint32_t)chain, (kChainTagNoise << 16) | 1u, n2, n3);
             const double e1 = se * n0, e2 = se * n1, e3 = se * n2;
             // eps K + sum_a eta_a sigma_a, times i
-            m2 Y = scale(K[j], cxd{eps, 0.0});
+            m2 Y = scale(K[j], cxd{e, 0.0});
             Y.a = Y.a + cxd{e3, 0.0};
             Y.b = Y.b + cxd{e1, -e2};
             Y.c = Y.c + cxd{e1, e2};
             Y.d = Y.d + cxd{-e3, 0.0};
             ch.U[j] = renorm(mul(exp_tl(scale(Y, cxd{0.0, 1.0})), ch.U[j]));
         }
-        ++step;
-        d_pre = chain_unorm(ch, s) / (2.0 * ch.n) - 1.0;
-        for (int ic = 0; ic < a.n_cool; ++ic) chain_cool_step(a, ch, s);
-        const double un = chain_unorm(ch, s);
-        d = un / (2.0 * ch.n) - 1.0;
-        const m2 Pt = chain_product(ch, s);
-        L = {0.5 * (Pt.a.re + Pt.d.re), 0.5 * (Pt.a.im + Pt.d.im)};
-        if (!isfinite(un) || !isfinite(L.re) || !isfinite(L.im)) {
-            status = 1;
-            break;
+        const double dp = chain_unorm(ch, g, s) / (2.0 * ch.n) - 1.0;
+        for (int ic = 0; ic < a.n_cool; ++ic) chain_cool_step(a, ch, g, s);
+        const double un = chain_unorm(ch, g, s);
+        const m2 Pt = chain_product(ch, g, s);
+        if (live) {
+            eps = e;
+            ++step;
+            d_pre = dp;
+            d = un / (2.0 * ch.n) - 1.0;
+            L = {0.5 * (Pt.a.re + Pt.d.re), 0.5 * (Pt.a.im + Pt.d.im)};
+            if (!isfinite(un) || !isfinite(L.re) || !isfinite(L.im)) {
+                status = 1;
+            } else {
+                sL_re += L.re;
+                sL_im += L.im;
+                sd += d;
+                ++done;
+                if (a.record && i < a.obs_cap && g.lt == 0) {
+                    double* o = a.obs + ((size_t)i * a.n_chains + chain) * kChainObs;
+                    o[0] = L.re;
+                    o[1] = L.im;
+                    o[2] = d;
+                    o[3] = eps;
+                    o[4] = kmax;
+                    o[5] = d_pre;
+                }
+            }
         }
-        sL_re += L.re;
-        sL_im += L.im;
-        sd += d;
-        ++done;
-        if (a.record && i < a.obs_cap && threadIdx.x == 0) {
-            double* o = a.obs + ((size_t)i * a.n_chains + chain) * kChainObs;
-            o[0] = L.re;
-            o[1] = L.im;
-            o[2] = d;
-            o[3] = eps;
-            o[4] = kmax;
-            o[5] = d_pre;
-        }
+        if (block_all_true(status != 0, s)) break;  // workgroup-uniform
     }
-    if (status == 0) chain_store(a, chain, ch);  // a runaway step leaves the links as they were
-    if (threadIdx.x == 0) {
+    if (!exists) return;
+    if (status == 0) chain_store(a, chain, ch);  // a runaway leaves the links as they were
+    if (g.lt == 0) {
         cc->step = step;
         cc->bound = bound;
         cc->status = status;
@@ -564,33 +620,39 @@ __global__ void __launch_bounds__(kChainBlock) k_chain_run(ChainArgs a, int n_st
 }
 
 // the drift of every link (K[chain][k][8]) and K_max (ctrl.kmax)
-__global__ void __launch_bounds__(kChainBlock) k_chain_drift(ChainArgs a)
+template <int B, int T>
+__global__ void __launch_bounds__(B) k_chain_drift(ChainArgs a)
 {
-    __shared__ ChainLds s;
-    const int chain = blockIdx.x;
+    __shared__ ChainLds<B> s;
+    const Seg g = make_seg(T);
+    const int chain = chain_of(g, B);
     Chain ch;
-    chain_load(a, chain, ch);
+    chain_load(a, chain, g, ch);
     m2 K[kChainPerThread];
-    const double kmax = chain_drift(a, ch, s, K);
+    const double kmax = chain_drift(a, ch, g, s, K);
+    if (chain >= a.n_chains) return;
     double* base = a.K + (size_t)chain * a.n * 8;
 #pragma unroll
     for (int j = 0; j < kChainPerThread; ++j)
         if (ch.valid(j)) store_link(base + (size_t)(ch.k0 + j) * 8, K[j]);
-    if (threadIdx.x == 0) a.ctrl[chain].kmax = kmax;
+    if (g.lt == 0) a.ctrl[chain].kmax = kmax;
 }
 
 // n_cool cooling steps of every chain, then L and d into the control block
-__global__ void __launch_bounds__(kChainBlock) k_chain_cool(ChainArgs a)
+template <int B, int T>
+__global__ void __launch_bounds__(B) k_chain_cool(ChainArgs a)
 {
-    __shared__ ChainLds s;
-    const int chain = blockIdx.x;
+    __shared__ ChainLds<B> s;
+    const Seg g = make_seg(T);
+    const int chain = chain_of(g, B);
     Chain ch;
-    chain_load(a, chain, ch);
-    for (int ic = 0; ic < a.n_cool; ++ic) chain_cool_step(a, ch, s);
-    const double un = chain_unorm(ch, s);
-    const m2 Pt = chain_product(ch, s);
+    chain_load(a, chain, g, ch);
+    for (int ic = 0; ic < a.n_cool; ++ic) chain_cool_step(a, ch, g, s);
+    const double un = chain_unorm(ch, g, s);
+    const m2 Pt = chain_product(ch, g, s);
+    if (chain >= a.n_chains) return;
     chain_store(a, chain, ch);
-    if (threadIdx.x == 0) {
+    if (g.lt == 0) {
         ChainCtrl* cc = a.ctrl + chain;
         cc->d = un / (2.0 * ch.n) - 1.0;
         cc->L_re = 0.5 * (Pt.a.re + Pt.d.re);
@@ -600,15 +662,17 @@ __global__ void __launch_bounds__(kChainBlock) k_chain_cool(ChainArgs a)
 }
 
 // L and d of every chain into the control block
-__global__ void __launch_bounds__(kChainBlock) k_chain_measure(ChainArgs a)
+template <int B, int T>
+__global__ void __launch_bounds__(B) k_chain_measure(ChainArgs a)
 {
-    __shared__ ChainLds s;
-    const int chain = blockIdx.x;
+    __shared__ ChainLds<B> s;
+    const Seg g = make_seg(T);
+    const int chain = chain_of(g, B);
     Chain ch;
-    chain_load(a, chain, ch);
-    const double un = chain_unorm(ch, s);
-    const m2 Pt = chain_product(ch, s);
-    if (threadIdx.x == 0) {
+    chain_load(a, chain, g, ch);
+    const double un = chain_unorm(ch, g, s);
+    const m2 Pt = chain_product(ch, g, s);
+    if (chain < a.n_chains && g.lt == 0) {
         ChainCtrl* cc = a.ctrl + chain;
         cc->d = un / (2.0 * ch.n) - 1.0;
         cc->L_re = 0.5 * (Pt.a.re + Pt.d.re);
@@ -616,42 +680,72 @@ __global__ void __launch_bounds__(kChainBlock) k_chain_measure(ChainArgs a)
     }
 }
 
+// threads per chain: the smallest power of two T with kChainPerThread T >= n
+int chain_threads(int n)
+{
+    int T = 1;
+    while (T * kChainPerThread < n) T *= 2;
+    return T;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// launchers (one workgroup per chain)
+// launchers: chains of up to 256 links in 64-thread workgroups (64 / T chains
+// each), longer ones in 256-thread workgroups (256 / T chains each)
+
+#define CHAIN_CASE(KERNEL, TT, ...)                                                                     \
+    case TT: {                                                                                          \
+        constexpr int B = TT <= 64 ? 64 : 256;                                                          \
+        hipLaunchKernelGGL((KERNEL<B, TT>), dim3((a.n_chains + B / TT - 1) / (B / TT)), dim3(B), 0, st, \
+                           __VA_ARGS__);                                                                \
+        break;                                                                                          \
+    }
+
+// one kernel instance per chain width T (loops over the chain's threads unroll)
+#define CHAIN_LAUNCH(KERNEL, ...)                                                                       \
+    do {                                                                                                \
+        switch (chain_threads(a.n)) {                                                                   \
+            CHAIN_CASE(KERNEL, 1, __VA_ARGS__)                                                          \
+            CHAIN_CASE(KERNEL, 2, __VA_ARGS__)                                                          \
+            CHAIN_CASE(KERNEL, 4, __VA_ARGS__)                                                          \
+            CHAIN_CASE(KERNEL, 8, __VA_ARGS__)                                                          \
+            CHAIN_CASE(KERNEL, 16, __VA_ARGS__)                                                         \
+            CHAIN_CASE(KERNEL, 32, __VA_ARGS__)                                                         \
+            CHAIN_CASE(KERNEL, 64, __VA_ARGS__)                                                         \
+            CHAIN_CASE(KERNEL, 128, __VA_ARGS__)                                                        \
+            CHAIN_CASE(KERNEL, 256, __VA_ARGS__)                                                        \
+            default: return hipErrorInvalidValue;                                                       \
+        }                                                                                               \
+    } while (0)
 
 hipError_t chain_launch_init(const ChainArgs& a, double sx, double sy, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chain_init, dim3((a.n + kChainBlock - 1) / kChainBlock, a.n_chains), dim3(kChainBlock), 0, st,
-                       a, sx, sy);
+    hipLaunchKernelGGL(k_chain_init, dim3((a.n + 255) / 256, a.n_chains), dim3(256), 0, st, a, sx, sy);
     return hipGetLastError();
 }
 
-hipError_t chain_launch_run(const ChainArgs& a, int n_steps, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+hipError_t chain_launch_run(const ChainArgs& a, int n_steps, hipStream_t st)
 {
-    if (ev0)
-        hipExtLaunchKernelGGL(k_chain_run, dim3(a.n_chains), dim3(kChainBlock), 0, st, ev0, ev1, 0, a, n_steps);
-    else
-        hipLaunchKernelGGL(k_chain_run, dim3(a.n_chains), dim3(kChainBlock), 0, st, a, n_steps);
+    CHAIN_LAUNCH(k_chain_run, a, n_steps);
     return hipGetLastError();
 }
 
 hipError_t chain_launch_drift(const ChainArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chain_drift, dim3(a.n_chains), dim3(kChainBlock), 0, st, a);
+    CHAIN_LAUNCH(k_chain_drift, a);
     return hipGetLastError();
 }
 
 hipError_t chain_launch_cool(const ChainArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chain_cool, dim3(a.n_chains), dim3(kChainBlock), 0, st, a);
+    CHAIN_LAUNCH(k_chain_cool, a);
     return hipGetLastError();
 }
 
 hipError_t chain_launch_measure(const ChainArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chain_measure, dim3(a.n_chains), dim3(kChainBlock), 0, st, a);
+    CHAIN_LAUNCH(k_chain_measure, a);
     return hipGetLastError();
 }
 

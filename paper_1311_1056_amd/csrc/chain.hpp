@@ -15,7 +15,7 @@
 
 namespace clgc {
 
-constexpr int kChainBlock = 256;      // threads per chain
+constexpr int kChainBlock = 256;      // most threads per chain (and per workgroup)
 constexpr int kChainPerThread = 4;    // links per thread
 constexpr int kChainMaxLinks = kChainBlock * kChainPerThread;
 constexpr int kChainObs = 6;          // Re L, Im L, d, eps, kmax, d before cooling

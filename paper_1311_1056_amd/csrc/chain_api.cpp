@@ -15,7 +15,7 @@
 
 namespace clgc {
 hipError_t chain_launch_init(const ChainArgs& a, double sx, double sy, hipStream_t st);
-hipError_t chain_launch_run(const ChainArgs& a, int n_steps, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t chain_launch_run(const ChainArgs& a, int n_steps, hipStream_t st);
 hipError_t chain_launch_drift(const ChainArgs& a, hipStream_t st);
 hipError_t chain_launch_cool(const ChainArgs& a, hipStream_t st);
 hipError_t chain_launch_measure(const ChainArgs& a, hipStream_t st);
@@ -200,7 +200,7 @@ cl_status cl_chain_run(cl_chain* ch, const cl_step_desc* step, const cl_cool_des
     cl_status st = set_params(ch, step, cool);
     if (st) return st;
     ch->a.record = record != 0;
-    HIP_TRY(chain_launch_run(ch->a, n_steps, ch->stream, nullptr, nullptr));
+    HIP_TRY(chain_launch_run(ch->a, n_steps, ch->stream));
     if (record) ch->recorded = n_steps;
     return CL_OK;
 }

@@ -160,6 +160,46 @@ def test_chains_are_independent_and_resumable(cl):
     b.close()
 
 
+@pytest.mark.parametrize("n", [4, 100, 300])
+def test_chain_does_not_depend_on_batch(cl, n):
+    """Short chains share a workgroup (T threads each, 64 / T or 256 / T per
+    workgroup): a chain's result equals, bit for bit, that of the same chain
+    run in a batch of another size."""
+    say("chain batch independence", n)
+    nc = 70
+    links = sl2c_links(np.random.default_rng(30 + n), (nc, n), 0.3, 0.01)
+    out = []
+    for m in (nc, 3):
+        ch = cl.Chain(n, m, 1.5 + 0.7j, seed=4, obs_cap=3)
+        ch.set_links(links[:m])
+        ch.run(3, 1e-2, True, 4, 1e-2, 1.0, 2, record=True)
+        out.append((ch.get_links(), ch.record(3), ch.measure()))
+        ch.close()
+    assert np.array_equal(out[0][0][:3], out[1][0])
+    assert np.array_equal(out[0][1][:, :3], out[1][1])
+    assert all(x["status"] == 0 for x in out[0][2])
+    assert [x["mean_L"] for x in out[0][2][:3]] == [x["mean_L"] for x in out[1][2]]
+
+
+def test_many_workgroups_of_short_chains_match_oracle(cl, orc):
+    """n = 4 (one thread per chain, 64 chains per workgroup) over three
+    workgroups, the last one partly filled."""
+    say("chain short, 3 workgroups")
+    n, nc, beta, seed = 4, 130, 2.0 - 0.4j, 12
+    links = sl2c_links(np.random.default_rng(13), (nc, n))
+    ch = cl.Chain(n, nc, beta, seed=seed, obs_cap=2)
+    ch.set_links(links)
+    ch.run(2, 1e-2, True, 3, 1e-2, 1.0, 1, record=True)
+    U = ch.get_links()
+    rec = ch.record(2)
+    for c in (0, 63, 64, 127, 128, 129):
+        ref = links[c].copy()
+        rc, obs, _ = orc.chain_run(ref, beta, seed, c, 2, 1e-2, True, 3, 1e-2, 1.0, 1)
+        assert rc == 0 and relerr(U[c], ref) < 1e-12, (c, relerr(U[c], ref))
+        assert np.allclose(rec[:, c], obs, rtol=1e-12, atol=1e-13)
+    ch.close()
+
+
 def test_runaway_chain_is_frozen_alone(cl):
     say("chain runaway")
     n = 6

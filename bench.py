@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--served-runs", type=int, default=256, help="runs in the served mix (0: skip)")
     ap.add_argument("--served-budget-mb", type=int, default=2048)
+    ap.add_argument("--chain-only", action="store_true",
+                    help="only run the SU(2) Polyakov-chain leg (for profiling its kernel)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -428,6 +430,111 @@ def alone_vs_batched(args, n=32):
             "batched_s": round(tb, 3), "alone_s": round(ta, 3)}
 
 
+def chain_cost(n_cool, mode):
+    """Algorithmic flops of one SU(2)-chain link-update: one CL update of one
+    link with its share of the n_cool cooling steps and of the measurement,
+    counted for a work-efficient schedule (a 2x2 complex product = 4 complex
+    products + 4 complex FMAs = 56 flops; Box-Muller transcendentals not
+    counted).  Drift: prefix, suffix and loop product per link (3 products),
+    i beta TL(P) and its norm (44).  Update: eps K + noise and the factor i
+    (54), the 2x2 exponential (norm, invariant, two 12-term complex series,
+    assembly: 274), the product (56), det renormalisation (51).  Two unitarity
+    norms (32).  Cooling step: TL(U U^dag - W^dag W) (62), the scale (3), the
+    closed Hermitian exponential pair (9-term real series: 60), the two
+    Hermitian-times-general products (80), the Omega / Omega^-1 entries (4),
+    plus the D_1 norm (16) or the D_2 gradient sum (6).  Measurement: the
+    ordered product (56)."""
+    prod = 56
+    drift = 3 * prod + 44
+    update = 54 + 274 + prod + 51
+    cool = 62 + 3 + 60 + 80 + 4 + (16 if mode == 1 else 6 if mode == 2 else 0)
+    return drift + update + 32 + n_cool * cool + prod
+
+
+def chain_workload(args):
+    """SU(2) Polyakov chain, S = -(beta/2) Tr(U_1 ... U_N), complex beta =
+    2 + i, CL with adaptive step and D_2 cooling (alpha = 1, eps_c = eps0),
+    unitary start (sigma 0.3 / 0).  Throughput at N = 10, 100 and 1000 links
+    (about 10^6 links each; eps0 = 5e-3, 10 cooling steps per update), and
+    <S> = -beta <Tr P / 2> (Langevin-time averages, 1024 chains of N = 10)
+    against the exact one-link value -beta I_2(beta) / I_1(beta): versus eps0
+    with its linear extrapolation to eps = 0 (10 D_2 steps), and versus the
+    number of cooling steps for D_0 and D_2 at eps0 = 1e-3."""
+    import numpy as np
+    import scipy.special
+    import torch
+    import paper_1311_1056_amd as cl
+    beta = 2.0 + 1.0j
+    out = {"workload": "SU(2) Polyakov chain, beta = 2 + 1i, adaptive eps0 = 5e-3, 10 D2 cooling steps "
+                       "(alpha = 1, eps_c = eps0) per update, FP64", "throughput": []}
+    eps = 5e-3
+    for n, n_chains, steps in ((10, 102400, 20), (100, 10240, 20), (1000, 1024, 20)):
+        ch = cl.Chain(n, n_chains, beta, seed=1)
+        ch.init(0.3, 0.0)
+        ch.run(2, eps, True, 10, eps, 1.0, cl.CL_ALPHA_GRAD)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ch.run(steps, eps, True, 10, eps, 1.0, cl.CL_ALPHA_GRAD)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        m = ch.measure()
+        ch.close()
+        lu = n * n_chains * steps
+        tflops = chain_cost(10, 2) * lu / (ms * 1e-3) / 1e12
+        out["throughput"].append({
+            "n_links": n, "chains": n_chains, "steps": steps, "ms": round(ms, 3),
+            "link_updates_per_s": round(lu / (ms * 1e-3), 1),
+            "roofline": {"bound": "alu", "kernel": "k_chain_run", "achieved": round(tflops, 2),
+                         "peak": VALU_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(tflops / VALU_FP64_TFLOPS, 4),
+                         "alg_flops_per_link_update": chain_cost(10, 2), "traffic": None},
+            "chains_ok": sum(x["status"] == 0 for x in m)})
+        progress(f"chain N={n}: {lu / (ms * 1e-3) / 1e9:.2f} G link-updates/s")
+    exact = complex(-beta * scipy.special.iv(2, beta) / scipy.special.iv(1, beta))
+
+    def point(eps0, n_cool, mode, scale):
+        ch = cl.Chain(10, 1024, beta, seed=7)
+        ch.init(0.3, 0.0)
+        ch.run(int(2.5 / eps0), eps0, True, n_cool, eps0, 1.0, mode)        # Langevin time 2.5
+        ch.run(int(scale / eps0), eps0, True, n_cool, eps0, 1.0, mode)      # Langevin time `scale`
+        m = [x for x in ch.measure() if x["status"] == 0]
+        ch.close()
+        S = np.array([-beta * x["mean_L"] for x in m])
+        k = max(len(S), 1)
+        return {"eps0": eps0, "n_cool": n_cool, "chains_ok": len(m),
+                "S": [round(S.mean().real, 4), round(S.mean().imag, 4)],
+                "err": [round(S.real.std() / np.sqrt(k), 4), round(S.imag.std() / np.sqrt(k), 4)],
+                "d": float(f"{np.mean([x['mean_d'] for x in m]):.3e}") if m else None}
+
+    vs_eps = [point(e, 10, cl.CL_ALPHA_GRAD, 15.0) for e in (4e-3, 2e-3, 1e-3, 5e-4)]
+    x = np.array([p["eps0"] for p in vs_eps])
+    fit = {}
+    for c, part in ((0, "re"), (1, "im")):
+        y = np.array([p["S"][c] for p in vs_eps])
+        w = 1.0 / np.array([max(p["err"][c], 1e-4) for p in vs_eps]) ** 2
+        A = np.stack([np.ones_like(x), x], 1)
+        cov = np.linalg.inv(A.T @ (A * w[:, None]))
+        coef = cov @ (A.T @ (w * y))
+        fit[part] = [round(float(coef[0]), 4), round(float(np.sqrt(cov[0, 0])), 4)]
+    progress("chain eps extrapolation done")
+    vs_cool = []
+    for mode, name in ((cl.CL_ALPHA_FIXED, "D0"), (cl.CL_ALPHA_GRAD, "D2")):
+        for n_cool in (0, 1, 3, 10, 30):
+            if n_cool == 0 and mode != cl.CL_ALPHA_FIXED:
+                continue
+            p = point(1e-3, n_cool, mode, 15.0)
+            p["mode"] = name
+            vs_cool.append(p)
+    out["convergence"] = {"n_links": 10, "chains": 1024, "langevin_time": {"therm": 2.5, "measured": 15.0},
+                          "exact_S": [round(exact.real, 4), round(exact.imag, 4)],
+                          "vs_eps_D2_ncool10": vs_eps,
+                          "extrapolated_S_eps0": {"re": fit["re"], "im": fit["im"]},
+                          "vs_cooling_steps_eps1e-3": vs_cool}
+    progress("chain convergence done")
+    return out
+
+
 def copy_calibration(mib):
     import torch
     n = mib * 1024 * 1024 // 4
@@ -457,6 +564,9 @@ def main():
         sys.exit(2)
     if args.copy_calib:
         copy_calibration(args.copy_calib)
+        return
+    if args.chain_only:
+        print(json.dumps({"chain": chain_workload(args)}), flush=True)
         return
     res = run_gpu(args, args.precision)
     rf, kernels, rfs = roofline(res, args.precision, args.theta)
@@ -499,6 +609,7 @@ def main():
         progress("theta points done")
         out["cooling_modes"] = cooling_modes(args)
         progress("cooling modes done")
+        out["chain"] = chain_workload(args)
     if args.served_runs > 0 and args.precision == "fp64":
         out["served"] = served(args, res["value"], args.served_runs, 0.7)
         progress("served mix at 0.7x done")

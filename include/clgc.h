@@ -265,9 +265,13 @@ typedef struct {
     double d;            /* (1/2n) sum_k Tr(U U^dag - 1), after cooling */
     double d_pre;        /* the same before the cooling of the last step */
     double eps, kmax;    /* of the last CL step */
-    double sum_L[2];     /* sums of L and d over the steps of the last cl_chain_run */
-    double sum_d;
+    double sum_L[2];     /* Langevin-time integrals sum_n eps_n L_n and sum_n eps_n d_n over */
+    double sum_d;        /* the steps of the last cl_chain_run (an adaptive step visits */
+                         /* configurations of small eps more often: the time average     */
+                         /* sum / t_sum is the equilibrium estimate, the plain step      */
+                         /* average is not) */
     double n_sum;        /* steps in those sums */
+    double t_sum;        /* their Langevin time sum_n eps_n */
 } cl_chain_obs;
 
 /* Device bytes for the chains, their control blocks and obs_cap steps of record.

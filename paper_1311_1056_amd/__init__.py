@@ -77,7 +77,7 @@ class cl_chain_obs(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("L", ctypes.c_double * 2), ("d", ctypes.c_double), ("d_pre", ctypes.c_double),
                 ("eps", ctypes.c_double), ("kmax", ctypes.c_double), ("sum_L", ctypes.c_double * 2),
-                ("sum_d", ctypes.c_double), ("n_sum", ctypes.c_double)]
+                ("sum_d", ctypes.c_double), ("n_sum", ctypes.c_double), ("t_sum", ctypes.c_double)]
 
 
 class ClError(RuntimeError):
@@ -414,17 +414,18 @@ class Chain:
         return K.reshape(self.n_chains, self.n_links, 8), km
 
     def measure(self):
-        """Per chain: dict of step, status, L, d, d_pre, eps, kmax, mean_L, mean_d (means over
-        the steps of the last run)."""
+        """Per chain: dict of step, status, L, d, d_pre, eps, kmax, n_sum, t_sum and
+        mean_L, mean_d: Langevin-time averages (each step weighted by its eps) over the
+        steps of the last run."""
         buf = (cl_chain_obs * self.n_chains)()
         _check(lib.cl_chain_measure(self.handle, buf, self.n_chains))
         out = []
         for o in buf:
-            n = o.n_sum
+            t = o.t_sum
             out.append({"step": o.step, "status": o.status, "L": complex(o.L[0], o.L[1]), "d": o.d,
-                        "d_pre": o.d_pre, "eps": o.eps, "kmax": o.kmax, "n_sum": n,
-                        "mean_L": complex(o.sum_L[0], o.sum_L[1]) / n if n else complex("nan"),
-                        "mean_d": o.sum_d / n if n else float("nan")})
+                        "d_pre": o.d_pre, "eps": o.eps, "kmax": o.kmax, "n_sum": o.n_sum, "t_sum": t,
+                        "mean_L": complex(o.sum_L[0], o.sum_L[1]) / t if t > 0 else complex("nan"),
+                        "mean_d": o.sum_d / t if t > 0 else float("nan")})
         return out
 
     def record(self, n_steps):

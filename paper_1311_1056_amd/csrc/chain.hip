@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
     double bound = exists ? cc->bound : 0.0;
     Chain ch;
     chain_load(a, chain, g, ch);
-    double sL_re = 0.0, sL_im = 0.0, sd = 0.0, eps = 0.0, kmax = 0.0, d_pre = 0.0, d = 0.0;
+    double sL_re = 0.0, sL_im = 0.0, sd = 0.0, st = 0.0, eps = 0.0, kmax = 0.0, d_pre = 0.0, d = 0.0;
     cxd L = {0.0, 0.0};
     int done = 0;
     for (int i = 0; i < n_steps; ++i) {
@@ -583,9 +583,12 @@ __global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
             if (!isfinite(un) || !isfinite(L.re) || !isfinite(L.im)) {
                 status = 1;
             } else {
-                sL_re += L.re;
-                sL_im += L.im;
-                sd += d;
+                // Langevin-time integrals: with an adaptive step the chain
+                // spends more steps where eps is small, so each step weighs eps
+                sL_re = fma(eps, L.re, sL_re);
+                sL_im = fma(eps, L.im, sL_im);
+                sd = fma(eps, d, sd);
+                st += eps;
                 ++done;
                 if (a.record && i < a.obs_cap && g.lt == 0) {
                     double* o = a.obs + ((size_t)i * a.n_chains + chain) * kChainObs;
@@ -616,6 +619,7 @@ __global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
         cc->sum_L_im = sL_im;
         cc->sum_d = sd;
         cc->sum_n = done;
+        cc->sum_t = st;
     }
 }
 

@@ -32,7 +32,9 @@ struct ChainCtrl {
     double eps, kmax;   // of the last CL step
     double d_pre, d;    // distance after the last update, after its cooling
     double L_re, L_im;  // Polyakov loop Tr(U_0 ... U_{n-1}) / 2 after the last step
-    double sum_L_re, sum_L_im, sum_d, sum_n;  // sums over the steps since the last reset
+    // eps-weighted sums (Langevin-time integrals) of L and d, the step count and
+    // the Langevin time, over the steps of the last run call
+    double sum_L_re, sum_L_im, sum_d, sum_n, sum_t;
 };
 
 // everything one launch needs, passed by value in the kernel arguments

@@ -253,6 +253,7 @@ cl_status cl_chain_measure(cl_chain* ch, cl_chain_obs* out, int cap)
         o.sum_L[1] = c[i].sum_L_im;
         o.sum_d = c[i].sum_d;
         o.n_sum = c[i].sum_n;
+        o.t_sum = c[i].sum_t;
     }
     return CL_OK;
 }

@@ -134,6 +134,13 @@ def test_trajectory_matches_oracle(cl, orc):
         assert np.allclose(rec[:, c], obs, rtol=1e-10, atol=1e-12)
     m = ch.measure()
     assert all(x["step"] == 20 and x["status"] == 0 and x["n_sum"] == 20 for x in m)
+    # the running means are Langevin-time averages: sum eps_n L_n / sum eps_n
+    for c in range(nc):
+        w = rec[:, c, 3]
+        assert abs(m[c]["t_sum"] - w.sum()) < 1e-15 * 20
+        ref = np.sum(w * (rec[:, c, 0] + 1j * rec[:, c, 1])) / w.sum()
+        assert abs(m[c]["mean_L"] - ref) < 1e-13
+        assert abs(m[c]["mean_d"] - np.sum(w * rec[:, c, 2]) / w.sum()) < 1e-13
     ch.close()
 
 
@@ -233,3 +240,30 @@ def test_real_beta_equilibrium_is_the_bessel_ratio(cl):
     assert abs(means.mean() - exact) < 4 * err + 0.005, (means.mean(), err, exact)
     assert max(abs(x["mean_L"].imag) for x in m) < 1e-12
     ch.close()
+
+
+def test_complex_beta_cooled_cl_converges_to_exact(cl):
+    """Complex beta = 2 + i, 10 links, adaptive step with 10 D_2 cooling steps
+    per update: the Langevin-time average of S = -beta Tr P / 2, linearly
+    extrapolated to eps = 0 from eps0 = 1e-3 and 5e-4 (the step-size bias is
+    O(eps)), equals the exact one-link value -beta I_2(beta) / I_1(beta)
+    (section on the SU(2) Polyakov chain and its reduction to one link)."""
+    say("chain complex beta convergence")
+    beta = 2.0 + 1.0j
+    exact = -beta * scipy.special.iv(2, beta) / scipy.special.iv(1, beta)
+    est = []
+    for eps, seed in ((1e-3, 17), (5e-4, 18)):
+        ch = cl.Chain(10, 1024, beta, seed=seed)
+        ch.init(0.3, 0.0)
+        ch.run(int(2.5 / eps), eps, True, 10, eps, 1.0, 2)
+        ch.run(int(10.0 / eps), eps, True, 10, eps, 1.0, 2)
+        m = ch.measure()
+        ch.close()
+        assert all(x["status"] == 0 for x in m)
+        S = np.array([-beta * x["mean_L"] for x in m])
+        est.append((S.mean(), S.real.std() / np.sqrt(len(S)), S.imag.std() / np.sqrt(len(S))))
+    (s1, r1, i1), (s2, r2, i2) = est
+    s0 = 2 * s2 - s1
+    er, ei = np.hypot(2 * r2, r1), np.hypot(2 * i2, i1)
+    assert abs(s0.real - exact.real) < 4 * er + 0.01, (s0, er, exact)
+    assert abs(s0.imag - exact.imag) < 4 * ei + 0.01, (s0, ei, exact)

@@ -98,28 +98,28 @@ __device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, i
     return gather_values<MAX>(ra.part + (size_t)j * nblk, nblk, lds);
 }
 
-// the cooling step's unitarity-norm partials, summed and broadcast to every
-// thread of the block
-__device__ __forceinline__ double gather_cool_all(const RunArgs& ra, double* lds)
+// the cooling step's unitarity-norm partials (n <= kMaxCoolBlocks) summed by
+// one wavefront on its own: each lane adds its values in index order, then a
+// butterfly; every wavefront of every block gets the same value, with no
+// barrier, so the sum can wait until a wavefront's link loads are in flight
+__device__ __forceinline__ double wave_cool_sum(const RunArgs& ra)
 {
-    __shared__ double s_all;
-    const double v = gather_values(ra.cpart, ra.nblk[KIND_COOL], lds);
-    if (threadIdx.x == 0) s_all = v;
-    __syncthreads();
-    const double r = s_all;
-    __syncthreads();
-    return r;
-}
-
-// The run's status read once for the whole block and broadcast, so that every
-// wave of the block takes the same branch even if the word changes meanwhile.
-__device__ __forceinline__ bool block_run_ok(const Ctrl* cr)
-{
-    __shared__ int s_ok;
-    __syncthreads();  // the previous logical block of this workgroup may still read s_ok
-    if (threadIdx.x == 0) s_ok = cr->status == ST_OK;
-    __syncthreads();
-    return s_ok != 0;
+    typedef __attribute__((address_space(1))) const double* gcd;
+    const gcd p = (gcd)ra.cpart;
+    const int n = ra.nblk[KIND_COOL];
+    const int lane = (int)threadIdx.x & 63;
+    double acc = 0.0;
+    for (int base = 0; base < n; base += 8 * 64) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * 64 + lane;
+            v[u] = i < n ? p[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    return wave_sum(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -787,33 +787,15 @@ __device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm
     herm_exp_pair(A, E, Ei);
 }
 
+// In both kernels the link loads are issued first: the run's state (status,
+// the unitarity norm entering the step, alpha) only sets the coefficient,
+// which is needed once G is formed, so its dependent reads overlap the loads.
 template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
 {
-    __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
-    // this run still cools in this iteration; block 0 of this launch may flag
-    // the run non-finite while other blocks start, so one thread reads the
-    // status for its whole block (every wave takes the same branch)
-    if (iter < ra.n_cool && block_run_ok(cr)) {
-        // unitarity norm entering the step: from the finalized update (step 0) or
-        // reduced here from the previous step's apply partials (every block
-        // reduces the same <= 512 values in the same order)
-        const double un = iter == 0 ? cr->unorm : gather_cool_all(ra, lds);
-        const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
-                                             : (ra.mode == 2 ? cr->alpha_cur : ra.alpha);
-        if (lb == 0 && threadIdx.x == 0) {
-            if (ra.mode != 2) cr->alpha_cur = alpha_ad;
-            cr->unorm = un;
-            if (!isfinite(un)) cr->status = ST_NONFINITE;
-            if (iter < kMaxCoolHist) {
-                cr->hist_alpha[iter] = alpha_ad;
-                cr->hist_un[iter] = un;
-                cr->hist_n = iter + 1;
-            }
-        }
-        const T coef = T(-4.0 * ra.eps_c * alpha_ad);
+    if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
         const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
         for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
@@ -827,9 +809,29 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
                 h_add_uudag(G, load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V));
                 h_sub_udagu(G, load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V));
             }
+            // Each wavefront reads the status for itself (there is no barrier
+            // here).  Within this launch the word changes only below, in block
+            // 0, when the norm that every wavefront computes identically is not
+            // finite: then every Omega is non-finite and nothing reads them.
+            const bool ok = cr->status == ST_OK;
+            // unitarity norm entering the step: from the finalized update (step 0)
+            // or the previous step's apply partials
+            const double un = iter == 0 ? cr->unorm : wave_cool_sum(ra);
+            const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
+                                                 : (ra.mode == 2 ? cr->alpha_cur : ra.alpha);
+            if (ok && lb == 0 && c == 0 && threadIdx.x == 0) {
+                if (ra.mode != 2) cr->alpha_cur = alpha_ad;
+                cr->unorm = un;
+                if (!isfinite(un)) cr->status = ST_NONFINITE;
+                if (iter < kMaxCoolHist) {
+                    cr->hist_alpha[iter] = alpha_ad;
+                    cr->hist_un[iter] = un;
+                    cr->hist_n = iter + 1;
+                }
+            }
             herm3<T> E, Ei;
-            site_omega(G, coef, E, Ei);
-            if (lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
+            site_omega(G, T(-4.0 * ra.eps_c * alpha_ad), E, Ei);
+            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
         }
     }
     CLGC_END_BLOCKS
@@ -841,10 +843,12 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
     __shared__ double lds[8];
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
-    if (iter < ra.n_cool && cr->status == ST_OK) {
-        const T coef = T(-4.0 * ra.eps_c * cr->alpha_cur);
+    if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
         const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
+        // (no kernel writes the status during this launch: every wavefront
+        // reads the same value, so the block reduction below is reached by all)
+        bool ok = true;
         double un = 0.0;
         for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
             const int t = c * kBlock + (int)threadIdx.x;
@@ -865,9 +869,10 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
                 h_add_uudag(G, Uf);
                 h_sub_udagu(G, Ub);
             }
+            ok = cr->status == ST_OK;
             herm3<T> E, Ei;
-            site_omega(G, coef, E, Ei);
-            if (lane_ok) {
+            site_omega(G, T(-4.0 * ra.eps_c * cr->alpha_cur), E, Ei);
+            if (ok && lane_ok) {
                 const mat3<T> Nf = h_mul(E, Uf);
                 const mat3<T> Nb = mul_h(Ub, Ei);
                 cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
@@ -880,7 +885,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
         // the cooled configuration
         double v[1] = {un};
         block_reduce<1>(v, lds);
-        if (threadIdx.x == 0) ra.cpart[lb] = v[0];
+        if (ok && threadIdx.x == 0) ra.cpart[lb] = v[0];
     }
     CLGC_END_BLOCKS
 }

@@ -526,12 +526,48 @@ def chain_workload(args):
             p = point(1e-3, n_cool, mode, 15.0)
             p["mode"] = name
             vs_cool.append(p)
+    out["cooling_vs_t"] = chain_cooling_curves()
+    progress("chain cooling curves done")
     out["convergence"] = {"n_links": 10, "chains": 1024, "langevin_time": {"therm": 2.5, "measured": 15.0},
                           "exact_S": [round(exact.real, 4), round(exact.imag, 4)],
                           "vs_eps_D2_ncool10": vs_eps,
                           "extrapolated_S_eps0": {"re": fit["re"], "im": fit["im"]},
                           "vs_cooling_steps_eps1e-3": vs_cool}
     progress("chain convergence done")
+    return out
+
+
+def chain_cooling_curves():
+    """Cooling alone on gauge-rotated unitary chains U_k = Omega_k V_k
+    Omega_{k+1}^-1 (64 chains, numpy seed 3, eps_c = 1e-3, alpha = 1): d(t)
+    for D_0, D_1, D_2 on N = 1000 links with the log-log slope of the last
+    decade of D_0 (the paper reports t^(-3/2)), and D_0 for N = 1 ... 1000
+    (the slowing down with the chain length)."""
+    import numpy as np
+    import paper_1311_1056_amd as cl
+    from tests.chainutil import gauge_rotated_chains
+    ts = (1, 3, 10, 30, 100, 300, 1000, 3000, 10000, 30000)
+
+    def curve(n, mode):
+        ch = cl.Chain(n, 64, 1.0)
+        ch.set_links(gauge_rotated_chains(64, n, 3))
+        d, t = [float(np.mean([x["d"] for x in ch.measure()]))], 0
+        for T in ts:
+            ch.cool(T - t, 1e-3, 1.0, mode)
+            t = T
+            m = ch.measure()
+            d.append(float(np.mean([x["d"] for x in m])))
+        ok = sum(x["status"] == 0 for x in m)
+        ch.close()
+        return {"d": [float(f"{v:.4e}") for v in d], "chains_ok": ok}
+
+    out = {"eps_c": 1e-3, "alpha": 1.0, "chains": 64, "t": [0] + list(ts), "n1000": {}, "D0_vs_n": {}}
+    for mode, name in ((0, "D0"), (1, "D1"), (2, "D2")):
+        out["n1000"][name] = curve(1000, mode)
+    d0 = out["n1000"]["D0"]["d"]
+    out["n1000"]["D0_slope_3000_to_30000"] = round(float(np.log(d0[-1] / d0[-3]) / np.log(10.0)), 3)
+    for n in (1, 2, 10, 100):
+        out["D0_vs_n"][f"n{n}"] = curve(n, 0)
     return out
 
 

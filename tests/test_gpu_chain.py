@@ -267,3 +267,37 @@ def test_complex_beta_cooled_cl_converges_to_exact(cl):
     er, ei = np.hypot(2 * r2, r1), np.hypot(2 * i2, i1)
     assert abs(s0.real - exact.real) < 4 * er + 0.01, (s0, er, exact)
     assert abs(s0.imag - exact.imag) < 4 * ei + 0.01, (s0, ei, exact)
+
+
+def test_cooling_of_gauge_rotated_chains_follows_the_paper(cl):
+    """Section on the chain model, its cooling exercise (gauge-rotated unitary
+    chains): with fixed alpha (D_0) d decays like t^(-3/2) on a chain of 1000
+    links, a chain of 2 links cools to d = 0 exponentially (the slowing down
+    sets in for longer chains), D_2 is far ahead of D_0 early on, and L is
+    conserved throughout.  64 chains per case."""
+    say("chain cooling d(t)")
+    from tests.chainutil import gauge_rotated_chains
+
+    def d_at(n, eps, mode, ts):
+        links = gauge_rotated_chains(64, n, 3)
+        ch = cl.Chain(n, 64, 1.0)
+        ch.set_links(links)
+        L0 = np.array([x["L"] for x in ch.measure()])
+        out, t = [], 0
+        for T in ts:
+            ch.cool(T - t, eps, 1.0, mode)
+            t = T
+            m = ch.measure()
+            assert all(x["status"] == 0 for x in m)
+            out.append(np.mean([x["d"] for x in m]))
+        assert np.max(np.abs(np.array([x["L"] for x in m]) - L0)) < 1e-10
+        ch.close()
+        return np.array(out)
+
+    d0 = d_at(1000, 1e-2, 0, (1000, 10000))
+    slope = np.log(d0[1] / d0[0]) / np.log(10.0)
+    assert abs(slope + 1.5) < 0.1, (slope, d0)
+    assert d_at(2, 1e-2, 0, (3000,))[0] < 1e-9
+    early0 = d_at(1000, 1e-3, 0, (300,))[0]
+    early2 = d_at(1000, 1e-3, 2, (300,))[0]
+    assert early2 < early0 / 10, (early0, early2)

@@ -217,3 +217,27 @@ def test_real_beta_equilibrium_is_the_bessel_ratio(orc):
     exact = scipy.special.iv(2, beta) / scipy.special.iv(1, beta)
     # O(eps) step bias is well below the statistical error at eps = 5e-3
     assert abs(m - exact) < 4 * err + 0.01, (m, err, exact)
+
+
+@pytest.mark.timeout(120)
+def test_chain_cooling_power_law(orc):
+    """Section on the chain model (figure of adaptive variants on a long
+    chain): cooling a gauge-rotated unitary chain with fixed alpha, d(t) decays
+    asymptotically like t^(-3/2).  (Linearised, cooling diffuses the gauge
+    field; for independent Omega_k the non-unitarity is its lattice gradient,
+    so d ~ sum_k k^2 exp(-c k^2 t) ~ t^(-3/2).)  16 chains of 100 links,
+    eps_c alpha = 1e-2, slope of log <d> between 300 and 3000 steps."""
+    from tests.chainutil import gauge_rotated_chains
+    links = gauge_rotated_chains(16, 100, 40)
+    d = np.zeros(2)
+    for c in range(16):
+        lk = links[c].copy()
+        L0 = orc.chain_measure(lk, 1.0)[0]
+        orc.chain_cool(lk, 300, 1e-2, 1.0, 0)
+        d[0] += orc.chain_measure(lk, 1.0)[1]
+        orc.chain_cool(lk, 2700, 1e-2, 1.0, 0)
+        L1, d1, _ = orc.chain_measure(lk, 1.0)
+        d[1] += d1
+        assert abs(L1 - L0) < 1e-11
+    slope = np.log(d[1] / d[0]) / np.log(10.0)
+    assert abs(slope + 1.5) < 0.2, slope

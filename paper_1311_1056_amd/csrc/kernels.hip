@@ -753,17 +753,20 @@ __device__ __forceinline__ herm3<T> load_herm(__amdgpu_buffer_rsrc_t rs, int h, 
 template <typename T>
 __device__ __forceinline__ void store_herm(__amdgpu_buffer_rsrc_t rs, int h, int Vh, int j0, const herm3<T>& H)
 {
-    const uint32_t lane = (uint32_t)h * (uint32_t)sizeof(T);
+    // (j0 may differ between lanes: it goes into the lane offset, since the
+    // scalar offset must be uniform -- a divergent one costs a loop over its
+    // distinct values)
+    const uint32_t lane = ((uint32_t)j0 * (uint32_t)Vh + (uint32_t)h) * (uint32_t)sizeof(T);
     const int es = Vh * (int)sizeof(T);
-    buf_store_scalar<T>(rs, lane, (j0 + 0) * es, H.d0);
-    buf_store_scalar<T>(rs, lane, (j0 + 1) * es, H.d1);
-    buf_store_scalar<T>(rs, lane, (j0 + 2) * es, H.d2);
-    buf_store_scalar<T>(rs, lane, (j0 + 3) * es, H.u01.re);
-    buf_store_scalar<T>(rs, lane, (j0 + 4) * es, H.u01.im);
-    buf_store_scalar<T>(rs, lane, (j0 + 5) * es, H.u02.re);
-    buf_store_scalar<T>(rs, lane, (j0 + 6) * es, H.u02.im);
-    buf_store_scalar<T>(rs, lane, (j0 + 7) * es, H.u12.re);
-    buf_store_scalar<T>(rs, lane, (j0 + 8) * es, H.u12.im);
+    buf_store_scalar<T>(rs, lane, 0 * es, H.d0);
+    buf_store_scalar<T>(rs, lane, 1 * es, H.d1);
+    buf_store_scalar<T>(rs, lane, 2 * es, H.d2);
+    buf_store_scalar<T>(rs, lane, 3 * es, H.u01.re);
+    buf_store_scalar<T>(rs, lane, 4 * es, H.u01.im);
+    buf_store_scalar<T>(rs, lane, 5 * es, H.u02.re);
+    buf_store_scalar<T>(rs, lane, 6 * es, H.u02.im);
+    buf_store_scalar<T>(rs, lane, 7 * es, H.u12.re);
+    buf_store_scalar<T>(rs, lane, 8 * es, H.u12.im);
 }
 
 // quad-reduced G (each lane holds its mu share) -> Omega = exp(coef TL(G)) and its inverse

@@ -427,6 +427,15 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
             const int nu = nn + (nn >= mu);
             const int Pl = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
             const int fo = dual_plane(Pl) * ra.V;
+            // The dual clover matrices at d1 = x + mu and at x do not depend on
+            // the sign: FP64 loads them once per plane (its overflow registers
+            // hold them); FP32 would spill and reloads them per sign.
+            constexpr bool kHoist = sizeof(T) == 8;
+            mat3<T> X1 = m_zero<T>(), X0 = m_zero<T>();
+            if (kHoist && th) {
+                X1 = load_mat(Fb, fo + link_off(ra, 0, d1), fs);
+                X0 = load_mat(Fb, fo + p * ra.Vh + h, fs);
+            }
             // unrolled over the sign: a compile-time s selects the raw link or its
             // adjugate
 #pragma unroll
@@ -450,7 +459,7 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                 } else {
                     const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(Pl));
                     const cx<T> cts = {sig * ct.re, sig * ct.im};
-                    mat3<T> Q = load_mat(Fb, fo + link_off(ra, 0, d1), fs);
+                    mat3<T> Q = kHoist ? X1 : load_mat(Fb, fo + link_off(ra, 0, d1), fs);
                     add_transported(Q, e1, load_mat(Fb, fo + link_off(ra, 0, d2), fs));
                     if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
                     const mat3<T> R = e1 * m_adj(load_mat(Ub, link_off(ra, mu, d3), us));
@@ -465,9 +474,9 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                     Q = m_scale(Q, cts);
                     m_mac(A, Q, Pm);
                     m_mac(B, Pa, Q);
-                    const mat3<T> X0 = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
-                    m_mac(A, Pm, X0);
-                    m_mac(B, X0, Pa);
+                    const mat3<T> X0s = m_scale(kHoist ? X0 : load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
+                    m_mac(A, Pm, X0s);
+                    m_mac(B, X0s, Pa);
                 }
             }
         }

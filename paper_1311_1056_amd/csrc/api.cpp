@@ -224,7 +224,6 @@ cl_status enqueue_cool(cl_lattice* lat, int n)
     for (int i = 0; i < n; ++i) {
         if (lat->args.mode == CL_ALPHA_GRAD) {
             TIMED(lat, CL_K_GRADNORM, launch_gradnorm(lat->L, lat->prec, i));
-            TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_GRAD, i));
         }
         TIMED(lat, CL_K_COOL_OMEGA, launch_cool(lat->L, lat->prec, 0, i));
         TIMED(lat, CL_K_COOL_APPLY, launch_cool(lat->L, lat->prec, 1, i));

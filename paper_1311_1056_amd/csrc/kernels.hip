@@ -98,15 +98,14 @@ __device__ __forceinline__ double gather_partials(const RunArgs& ra, int kind, i
     return gather_values<MAX>(ra.part + (size_t)j * nblk, nblk, lds);
 }
 
-// the cooling step's unitarity-norm partials (n <= kMaxCoolBlocks) summed by
-// one wavefront on its own: each lane adds its values in index order, then a
+// n <= kMaxCoolBlocks partials (the cooling step's unitarity norm, the D_2
+// gradient norm) summed by one wavefront on its own: each lane adds its values in index order, then a
 // butterfly; every wavefront of every block gets the same value, with no
 // barrier, so the sum can wait until a wavefront's link loads are in flight
-__device__ __forceinline__ double wave_cool_sum(const RunArgs& ra)
+__device__ __forceinline__ double wave_sum_of(const double* p_in, int n)
 {
     typedef __attribute__((address_space(1))) const double* gcd;
-    const gcd p = (gcd)ra.cpart;
-    const int n = ra.nblk[KIND_COOL];
+    const gcd p = (gcd)p_in;
     const int lane = (int)threadIdx.x & 63;
     double acc = 0.0;
     for (int base = 0; base < n; base += 8 * 64) {
@@ -121,6 +120,8 @@ __device__ __forceinline__ double wave_cool_sum(const RunArgs& ra)
     }
     return wave_sum(acc);
 }
+
+__device__ __forceinline__ double wave_cool_sum(const RunArgs& ra) { return wave_sum_of(ra.cpart, ra.nblk[KIND_COOL]); }
 
 // ---------------------------------------------------------------------------
 // logical-block iteration
@@ -829,12 +830,15 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
             // unitarity norm entering the step: from the finalized update (step 0)
             // or the previous step's apply partials
             const double un = iter == 0 ? cr->unorm : wave_cool_sum(ra);
+            // D_2 = mean |f_ax| from the gradient-norm pass just before (its
+            // partials, one per cooling logical block)
+            const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
             const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
-                                                 : (ra.mode == 2 ? cr->alpha_cur : ra.alpha);
+                                                 : (ra.mode == 2 ? ra.alpha / d2 : ra.alpha);
             if (ok && lb == 0 && c == 0 && threadIdx.x == 0) {
-                if (ra.mode != 2) cr->alpha_cur = alpha_ad;
+                cr->alpha_cur = alpha_ad;
                 cr->unorm = un;
-                if (!isfinite(un)) cr->status = ST_NONFINITE;
+                if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
                 if (iter < kMaxCoolHist) {
                     cr->hist_alpha[iter] = alpha_ad;
                     cr->hist_un[iter] = un;
@@ -903,34 +907,52 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
 }
 
 // D_2 = mean over (a, x) of |f_ax| on the configuration entering a cooling
-// step, f_ax = 2 Tr(lambda_a G_x); sets alpha_cur = alpha / D_2.
+// step, f_ax = 2 Tr(lambda_a G_x).  Two lanes per site (directions 0, 1 and
+// 2, 3, joined by one shuffle), on the cooling kernels' logical blocks: the
+// chunks of kBlock lanes are then exactly as many as the cooling chunks, so
+// every block (and every XCD) has work, and the next omega kernel's
+// wavefronts sum the <= kMaxCoolBlocks partials themselves.
 template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_gradnorm(const KArgs ka, int iter)
 {
     __shared__ double lds[8];
-    CLGC_FOR_BLOCKS(KIND_SITE)
+    CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
     if (ra.mode == 2 && iter < ra.n_cool && cr->status == ST_OK) {
+        const int nch = (2 * ra.V + kBlock - 1) / kBlock;
+        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
         double fs = 0.0;
-        if (tid < ra.V) {
-            const int p = tid >= ra.Vh;
-            const int h = tid - p * ra.Vh;
-            const Site x = site_coords(ra, p, h);
+        for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+            const int t = c * kBlock + (int)threadIdx.x;
+            const int sx = t >> 1, half = t & 1;
             herm3<T> G = h_zero<T>();
-#pragma unroll 1
-            for (int mu = 0; mu < 4; ++mu) {
-                h_add_uudag(G, ldU<T>(ra, mu, x));
-                h_sub_udagu(G, ldU<T>(ra, mu, site_move(ra, x, mu, -1)));
+            if (sx < ra.V) {
+                const int p = sx >= ra.Vh;
+                const Site x = site_coords(ra, p, sx - p * ra.Vh);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int mu = 2 * half + m;
+                    h_add_uudag(G, ldU<T>(ra, mu, x));
+                    h_sub_udagu(G, ldU<T>(ra, mu, site_move(ra, x, mu, -1)));
+                }
             }
-            const double r3 = 0.57735026918962576451;
-            fs = 4.0 * (fabs((double)G.u01.re) + fabs((double)G.u01.im) + fabs((double)G.u02.re) +
-                        fabs((double)G.u02.im) + fabs((double)G.u12.re) + fabs((double)G.u12.im)) +
-                 2.0 * fabs((double)G.d0 - (double)G.d1) +
-                 2.0 * r3 * fabs((double)G.d0 + (double)G.d1 - 2.0 * (double)G.d2);
+            G.d0 += __shfl_xor(G.d0, 1, 64);
+            G.d1 += __shfl_xor(G.d1, 1, 64);
+            G.d2 += __shfl_xor(G.d2, 1, 64);
+            G.u01 = {G.u01.re + __shfl_xor(G.u01.re, 1, 64), G.u01.im + __shfl_xor(G.u01.im, 1, 64)};
+            G.u02 = {G.u02.re + __shfl_xor(G.u02.re, 1, 64), G.u02.im + __shfl_xor(G.u02.im, 1, 64)};
+            G.u12 = {G.u12.re + __shfl_xor(G.u12.re, 1, 64), G.u12.im + __shfl_xor(G.u12.im, 1, 64)};
+            if (sx < ra.V && half == 0) {
+                const double r3 = 0.57735026918962576451;
+                fs += 4.0 * (fabs((double)G.u01.re) + fabs((double)G.u01.im) + fabs((double)G.u02.re) +
+                             fabs((double)G.u02.im) + fabs((double)G.u12.re) + fabs((double)G.u12.im)) +
+                      2.0 * fabs((double)G.d0 - (double)G.d1) +
+                      2.0 * r3 * fabs((double)G.d0 + (double)G.d1 - 2.0 * (double)G.d2);
+            }
         }
         double v[1] = {fs};
         block_reduce<1>(v, lds);
-        store_partials(ra, KIND_SITE, lb, v);
+        if (threadIdx.x == 0) ra.part[lb] = v[0];
     }
     CLGC_END_BLOCKS
 }
@@ -1056,16 +1078,6 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, i
                 c->unorm = tot;
                 if (it + 1 <= kMaxCoolHist) c->hist_un[it + 1] = tot;
                 if (!isfinite(tot)) c->status = ST_NONFINITE;
-            }
-            break;
-        }
-        case FIN_GRAD: {
-            if (!ok || ra.mode != 2 || iter >= ra.n_cool) break;
-            const double tot = gather_partials(ra, KIND_SITE, 0, lds);
-            if (threadIdx.x == 0) {
-                const double D = tot / (8.0 * ra.V);
-                c->alpha_cur = ra.alpha / D;
-                if (!(D > 0.0) || !isfinite(c->alpha_cur)) c->status = ST_NONFINITE;
             }
             break;
         }
@@ -1237,8 +1249,8 @@ hipError_t launch_cool(const Launch& L, int prec, int phase, int iter)
 
 hipError_t launch_gradnorm(const Launch& L, int prec, int iter)
 {
-    if (prec) CLGC_LAUNCH((k_gradnorm<float, FAST_>), KIND_SITE, iter);
-    else CLGC_LAUNCH((k_gradnorm<double, FAST_>), KIND_SITE, iter);
+    if (prec) CLGC_LAUNCH((k_gradnorm<float, FAST_>), KIND_COOL, iter);
+    else CLGC_LAUNCH((k_gradnorm<double, FAST_>), KIND_COOL, iter);
     return hipGetLastError();
 }
 

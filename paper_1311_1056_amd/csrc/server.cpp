@@ -243,7 +243,6 @@ cl_status enqueue_group_step(cl_server* s, int g, int max_nc, bool any_theta, bo
     for (int i = 0; i < max_nc; ++i) {
         if (any_grad) {
             HIP_TRY(launch_gradnorm(L, g, i));
-            HIP_TRY(launch_finalize(L, FIN_GRAD, i));
         }
         HIP_TRY(launch_cool(L, g, 0, i));
         HIP_TRY(launch_cool(L, g, 1, i));

@@ -23,6 +23,9 @@
  *
  * Parity pins (what fixes each function other than itself) live in
  * tests/test_oracle_*.py; each function below names its passage.
+ * Parity unpinned: none of these functions.  What no pin fixes is the
+ * absolute physics value of <P> and <Q> at given (beta, theta), which the
+ * paper's figures do not give in recoverable form.
  */
 #include "clgc_oracle.h"
 

@@ -497,9 +497,13 @@ __device__ __forceinline__ int chain_of(const Seg& g, int B) { return (int)block
 // U_k = exp(i sigma_a (x_a + i y_a)), x ~ N(0, sx), y ~ N(0, sy); fresh control block
 __global__ void __launch_bounds__(256) k_chain_init(ChainArgs a, double sx, double sy)
 {
-    const int chain = blockIdx.y;
-    const int k = blockIdx.x * 256 + (int)threadIdx.x;
-    if (k < a.n) {
+    // one lane per link of every chain (a one-dimensional grid: the chain count
+    // may exceed the limit of a grid's second dimension)
+    const size_t l = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (l >= (size_t)a.n * a.n_chains) return;
+    const int chain = (int)(l / a.n);
+    const int k = (int)(l - (size_t)chain * a.n);
+    {
         double p[8];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -725,7 +729,8 @@ int chain_threads(int n)
 
 hipError_t chain_launch_init(const ChainArgs& a, double sx, double sy, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chain_init, dim3((a.n + 255) / 256, a.n_chains), dim3(256), 0, st, a, sx, sy);
+    const size_t links = (size_t)a.n * a.n_chains;
+    hipLaunchKernelGGL(k_chain_init, dim3((unsigned)((links + 255) / 256)), dim3(256), 0, st, a, sx, sy);
     return hipGetLastError();
 }
 

@@ -57,6 +57,20 @@ def test_init_matches_oracle(cl, orc):
     ch.close()
 
 
+def test_init_of_many_chains(cl, orc):
+    """More chains than a grid's second dimension holds (70000 chains of 3
+    links): the start of sampled chains equals the oracle's."""
+    say("chain init, 70000 chains")
+    ch = cl.Chain(3, 70000, 1.0, seed=13)
+    ch.init(0.3, 0.05)
+    U = ch.get_links()
+    for c in (0, 65534, 65535, 65536, 69999):
+        assert relerr(U[c], orc.chain_init(3, c, 13, 0.3, 0.05)) < 1e-14, c
+    m = ch.measure()
+    assert all(x["status"] == 0 and x["step"] == 0 for x in m[65530:65540])
+    ch.close()
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 64, 257, 1000, 1024])
 def test_drift_matches_oracle(cl, orc, n):
     say("chain drift", n)

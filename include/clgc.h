@@ -250,7 +250,7 @@ typedef struct cl_chain cl_chain;
 
 typedef struct {
     int32_t n_links;     /* 1 .. 1024 */
-    int32_t n_chains;    /* >= 1 */
+    int32_t n_chains;    /* 1 .. 2^24 */
     double beta_re, beta_im;
     uint64_t seed;
     int32_t obs_cap;     /* steps of per-step record kept on the device (may be 0) */
@@ -290,13 +290,15 @@ cl_status cl_chain_init(cl_chain* ch, double sigma_x, double sigma_y);
 cl_status cl_chain_set_links(cl_chain* ch, const double* host, size_t n_doubles);
 cl_status cl_chain_get_links(cl_chain* ch, double* host, size_t n_doubles);
 /* n_steps CL steps of every chain, each followed by cool->n_steps cooling
- * steps (cool may be NULL: none) and a measurement, in one launch (one
- * workgroup per chain; the links stay on chip between steps).  Adaptive step
+ * steps (cool may be NULL: none) and a measurement, in one launch (a chain
+ * is owned by T threads of a workgroup, T the smallest power of two with
+ * 4 T >= n_links, and its links stay in registers between steps).  Adaptive step
  * eps = min(eps0, B/K_max) per chain, B fixed on its first step (drift_bound if
  * > 0).  record != 0 keeps (Re L, Im L, d, eps, kmax, d_pre) of every step in
  * the device record (n_steps <= obs_cap), read with cl_chain_record.  A chain
- * whose drift or norm turns non-finite keeps its last finite links and status
- * 1.  Asynchronous on the stream.
+ * whose drift, norm or loop turns non-finite gets status 1, keeps the links it
+ * had when the call started and is not advanced again; the other chains are
+ * not affected.  Asynchronous on the stream.
  * CL_EINVAL: n_steps < 0, record with n_steps > obs_cap, bad eps0/cooling. */
 cl_status cl_chain_run(cl_chain* ch, const cl_step_desc* step, const cl_cool_desc* cool, int n_steps, int record);
 /* cooling only: cool->n_steps steps of every chain (eq. (eq:24)), then L and d. */

@@ -172,8 +172,40 @@ def roofline(res, precision, theta):
     for k in sorted(costed, key=lambda k: -timing[k][0]):
         rf = kernel_roofline(k, timing[k][0], timing[k][1], V, rs, theta, precision, res["dims"])
         rf["share_of_step"] = round(timing[k][0] / total, 3)
+        if rf["bound"] == "hbm":
+            # practical ceiling at this size: a plain device copy of the same bytes
+            cus = copy_us(rf["alg_bytes_per_launch"])
+            rf["copy_same_bytes_us"] = round(cus, 2)
+            rf["frac_of_copy"] = round(cus / rf["avg_us"], 4)
         rfs.append(rf)
     return rfs[0], kernels, rfs
+
+
+_COPY_CACHE = {}
+
+
+def copy_us(total_bytes):
+    """Best-of-20 event-timed duration of a plain device copy (torch copy_)
+    that reads and writes total_bytes / 2 each."""
+    if total_bytes in _COPY_CACHE:
+        return _COPY_CACHE[total_bytes]
+    import torch
+    n = max(1, int(total_bytes // 16))
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(20):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, 1e3 * e0.elapsed_time(e1))
+    del a, b
+    _COPY_CACHE[total_bytes] = best
+    return best
 
 
 def traffic_for(kernel, precision, dims):

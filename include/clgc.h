@@ -292,7 +292,8 @@ cl_status cl_chain_get_links(cl_chain* ch, double* host, size_t n_doubles);
 /* n_steps CL steps of every chain, each followed by cool->n_steps cooling
  * steps (cool may be NULL: none) and a measurement, in one launch (a chain
  * is owned by T threads of a workgroup, T the smallest power of two with
- * 4 T >= n_links, and its links stay in registers between steps).  Adaptive step
+ * PT T >= n_links, PT = 2 up to 512 links and 4 above, and its links stay in
+ * registers between steps).  Adaptive step
  * eps = min(eps0, B/K_max) per chain, B fixed on its first step (drift_bound if
  * > 0).  record != 0 keeps (Re L, Im L, d, eps, kmax, d_pre) of every step in
  * the device record (n_steps <= obs_cap), read with cl_chain_record.  A chain

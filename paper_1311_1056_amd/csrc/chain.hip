@@ -3,8 +3,9 @@
 // model", action eq. (eq:s); cooling eq. (eq:24); distance eq. (d)).
 //
 // A chain of n <= 1024 links is owned by T threads of one workgroup for a
-// whole call (T the smallest power of two with 4 T >= n; short chains share a
-// workgroup): four links per thread live in registers, so a call of many CL
+// whole call (PT links per thread, two up to 512 links and four above; T the
+// smallest power of two with PT T >= n; short chains share a workgroup): the
+// links live in registers, so a call of many CL
 // steps reads and writes HBM once.  Per CL step:
 //   drift   K_k = -D_a S sigma_a = i beta TL(P_k), P_k = U_k ... U_{n-1} U_0 ... U_{k-1}
 //           (the loop opened at link k), from an inclusive prefix and an
@@ -165,8 +166,12 @@ __device__ __forceinline__ m2 get(const double (*arr)[B], int i)
 
 // ---------------------------------------------------------------------------
 // workgroup layout: a chain of n links is owned by T threads (the smallest
-// power of two with kChainPerThread T >= n), four consecutive links each; a
-// workgroup of B threads (64 for T <= 64, else 256) holds B / T chains.
+// power of two with PT T >= n), PT consecutive links each; a workgroup of B
+// threads (64 for T <= 64, else 256) holds B / T chains.  Two links per thread
+// keep a thread's state within 256 registers, two waves per SIMD, which the
+// dependent FP64 work of one thread needs to keep the SIMD busy; chains longer
+// than 512 links take four per thread (one wave per SIMD), which measured
+// faster there than 512 threads per chain with their longer scans.
 
 template <int B>
 struct ChainLds {
@@ -193,8 +198,9 @@ __device__ __forceinline__ Seg make_seg(int T)
     return g;
 }
 
+template <int PT>
 struct Chain {
-    m2 U[kChainPerThread];
+    m2 U[PT];
     int n, k0;  // chain length, first link of this thread
     __device__ bool valid(int j) const { return k0 + j < n; }
 };
@@ -243,14 +249,14 @@ __device__ __forceinline__ bool block_all_true(bool p, ChainLds<B>& s)
 }
 
 // E = M_0 ... M_t-1 and F = M_t+1 ... M_T-1, the chain's products before and
-// after this thread's links (M_t = U_k0 ... U_k0+3), from an inclusive prefix
+// after this thread's links (M_t = U_k0 ... U_k0+PT-1), from an inclusive prefix
 // and an inclusive suffix scan over the chain's threads (Hillis-Steele)
-template <int B>
-__device__ __forceinline__ void chain_ends(const Chain& ch, const Seg& g, ChainLds<B>& s, m2& E, m2& F)
+template <int B, int PT>
+__device__ __forceinline__ void chain_ends(const Chain<PT>& ch, const Seg& g, ChainLds<B>& s, m2& E, m2& F)
 {
     m2 M = m2_id();
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j)
+    for (int j = 0; j < PT; ++j)
         if (ch.valid(j)) M = mul(M, ch.U[j]);
     m2 I = M, S = M;
 #pragma unroll
@@ -274,29 +280,30 @@ __device__ __forceinline__ void chain_ends(const Chain& ch, const Seg& g, ChainL
     __syncthreads();
 }
 
-// The loop opened at each of this thread's links, P_j = U_j ... U_3 F E U_0 ...
-// U_j-1 (invalid links are the identity and need no test): with A_j = E U_0 ...
-// U_j-1 and B_j = U_j ... U_3 F, P_j = B_j A_j.
-__device__ __forceinline__ void chain_loops(const Chain& ch, const m2& E, const m2& F, m2 (&P)[kChainPerThread])
+// The loop opened at each of this thread's links, P_j = U_j ... U_PT-1 F E U_0
+// ... U_j-1 (invalid links are the identity and need no test): with A_j = E U_0
+// ... U_j-1 and B_j = U_j ... U_PT-1 F, P_j = B_j A_j.
+template <int PT>
+__device__ __forceinline__ void chain_loops(const Chain<PT>& ch, const m2& E, const m2& F, m2 (&P)[PT])
 {
-    m2 A[kChainPerThread], Bm[kChainPerThread];
+    m2 A[PT], Bm[PT];
     A[0] = E;
 #pragma unroll
-    for (int j = 1; j < kChainPerThread; ++j) A[j] = mul(A[j - 1], ch.U[j - 1]);
-    Bm[kChainPerThread - 1] = mul(ch.U[kChainPerThread - 1], F);
+    for (int j = 1; j < PT; ++j) A[j] = mul(A[j - 1], ch.U[j - 1]);
+    Bm[PT - 1] = mul(ch.U[PT - 1], F);
 #pragma unroll
-    for (int j = kChainPerThread - 2; j >= 0; --j) Bm[j] = mul(ch.U[j], Bm[j + 1]);
+    for (int j = PT - 2; j >= 0; --j) Bm[j] = mul(ch.U[j], Bm[j + 1]);
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) P[j] = mul(Bm[j], A[j]);
+    for (int j = 0; j < PT; ++j) P[j] = mul(Bm[j], A[j]);
 }
 
 // ordered product U_0 ... U_{n-1} (valid in every thread of the chain)
-template <int B>
-__device__ __forceinline__ m2 chain_product(const Chain& ch, const Seg& g, ChainLds<B>& s)
+template <int B, int PT>
+__device__ __forceinline__ m2 chain_product(const Chain<PT>& ch, const Seg& g, ChainLds<B>& s)
 {
     m2 M = m2_id();
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j)
+    for (int j = 0; j < PT; ++j)
         if (ch.valid(j)) M = mul(M, ch.U[j]);
     put(s.pre, g.t, M);
     __syncthreads();
@@ -310,20 +317,20 @@ __device__ __forceinline__ m2 chain_product(const Chain& ch, const Seg& g, Chain
     return r;
 }
 
-template <int B>
-__device__ __forceinline__ double chain_unorm(const Chain& ch, const Seg& g, ChainLds<B>& s)
+template <int B, int PT>
+__device__ __forceinline__ double chain_unorm(const Chain<PT>& ch, const Seg& g, ChainLds<B>& s)
 {
     double u = 0.0;
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j)
+    for (int j = 0; j < PT; ++j)
         if (ch.valid(j)) u += nrm2(ch.U[j]);
     return chain_all<false>(u, g, s);
 }
 
 // the drift K_j = i beta TL(P_j) of this thread's links and K_max of the chain
-template <int B>
-__device__ __forceinline__ double chain_drift(const ChainArgs& a, const Chain& ch, const Seg& g, ChainLds<B>& s,
-                                              m2 (&K)[kChainPerThread])
+template <int B, int PT>
+__device__ __forceinline__ double chain_drift(const ChainArgs& a, const Chain<PT>& ch, const Seg& g, ChainLds<B>& s,
+                                              m2 (&K)[PT])
 {
     m2 E, F;
     chain_ends(ch, g, s, E, F);
@@ -331,7 +338,7 @@ __device__ __forceinline__ double chain_drift(const ChainArgs& a, const Chain& c
     const cxd ib = {-a.beta_im, a.beta_re};  // i beta
     double kn2 = 0.0;
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) {
+    for (int j = 0; j < PT; ++j) {
         K[j] = scale(tl(K[j]), ib);
         if (ch.valid(j)) {
             double v = 0.5 * nrm2(K[j]);
@@ -396,17 +403,17 @@ __device__ __forceinline__ hexp herm_exp2(double g, cxd q)
 }
 
 // one Jacobi cooling step at eps_c alpha_ad chosen by the mode
-template <int B>
-__device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, const Seg& g, ChainLds<B>& s)
+template <int B, int PT>
+__device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain<PT>& ch, const Seg& g, ChainLds<B>& s)
 {
     // neighbours: link k-1 of this thread's first link (link n-1 for k = 0)
-    put(s.edge, g.t, ch.U[kChainPerThread - 1]);
-    if (ch.valid(0) && (ch.n - 1) / kChainPerThread == g.lt) {
+    put(s.edge, g.t, ch.U[PT - 1]);
+    if (ch.valid(0) && (ch.n - 1) / PT == g.lt) {
         // link n-1 by compile-time selects (a runtime index would put U in scratch)
-        const int jl = (ch.n - 1) % kChainPerThread;
+        const int jl = (ch.n - 1) % PT;
         m2 u = ch.U[0];
 #pragma unroll
-        for (int j = 1; j < kChainPerThread; ++j) u = pick(j == jl, ch.U[j], u);
+        for (int j = 1; j < PT; ++j) u = pick(j == jl, ch.U[j], u);
         put(s.suf, g.first, u);
     }
     __syncthreads();
@@ -416,11 +423,11 @@ __device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, c
     // G_k = TL(U U^dag - W^dag W) = [[g, q], [q*, -g]]: sum_a f_ak sigma_a = 4 TL(G_k)
     // (the trace, the difference of the two links' norms, is no direction of the
     // gauge orbit), f_1 = 4 Re q, f_2 = -4 Im q, f_3 = 4 g
-    double gd[kChainPerThread];
-    cxd q[kChainPerThread];
+    double gd[PT];
+    cxd q[PT];
     double un = 0.0, fsum = 0.0;
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) {
+    for (int j = 0; j < PT; ++j) {
         m2 W = prev0;
         if (j > 0) W = ch.U[j - 1];
         const m2& U = ch.U[j];
@@ -440,27 +447,27 @@ __device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, c
     if (a.mode == 1) D = chain_all<false>(un, g, s) / ch.n;
     if (a.mode == 2) D = chain_all<false>(fsum, g, s) / (3.0 * ch.n);
     const double c = -4.0 * a.eps_c * (a.alpha / D);
-    hexp Om[kChainPerThread];
+    hexp Om[PT];
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) Om[j] = herm_exp2(c * gd[j], cxd{c * q[j].re, c * q[j].im});
+    for (int j = 0; j < PT; ++j) Om[j] = herm_exp2(c * gd[j], cxd{c * q[j].re, c * q[j].im});
     s.edge[0][g.t] = Om[0].C;
     s.edge[1][g.t] = Om[0].Sg;
     s.edge[2][g.t] = Om[0].Sq.re;
     s.edge[3][g.t] = Om[0].Sq.im;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) {
+    for (int j = 0; j < PT; ++j) {
         if (!ch.valid(j)) continue;
         const int k = ch.k0 + j;
         // Omega^-1 of site k+1: this thread's next one, the next thread's first
         // (always of the same chain: the chain's last thread holds link n-1),
         // or, for k = n-1, the chain's first
         hexp On;
-        if (k + 1 == ch.n || j + 1 == kChainPerThread) {
+        if (k + 1 == ch.n || j + 1 == PT) {
             const int o = k + 1 == ch.n ? g.first : g.t + 1;
             On = hexp{s.edge[0][o], s.edge[1][o], cxd{s.edge[2][o], s.edge[3][o]}};
         } else {
-            On = Om[(j + 1) % kChainPerThread];
+            On = Om[(j + 1) % PT];
         }
         ch.U[j] = mulh(hmul(Om[j].fwd(), ch.U[j]), On.inv());
     }
@@ -469,23 +476,25 @@ __device__ __forceinline__ void chain_cool_step(const ChainArgs& a, Chain& ch, c
 
 // this thread's links of a chain; a chain index past the last (the padding
 // of the last workgroup) gets identity links and is never stored
-__device__ __forceinline__ void chain_load(const ChainArgs& a, int chain, const Seg& g, Chain& ch)
+template <int PT>
+__device__ __forceinline__ void chain_load(const ChainArgs& a, int chain, const Seg& g, Chain<PT>& ch)
 {
     ch.n = a.n;
-    ch.k0 = g.lt * kChainPerThread;
+    ch.k0 = g.lt * PT;
     const double* base = a.links + (size_t)chain * a.n * 8;
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j) {
+    for (int j = 0; j < PT; ++j) {
         ch.U[j] = m2_id();
         if (chain < a.n_chains && ch.valid(j)) ch.U[j] = load_link(base + (size_t)(ch.k0 + j) * 8);
     }
 }
 
-__device__ __forceinline__ void chain_store(const ChainArgs& a, int chain, const Chain& ch)
+template <int PT>
+__device__ __forceinline__ void chain_store(const ChainArgs& a, int chain, const Chain<PT>& ch)
 {
     double* base = a.links + (size_t)chain * a.n * 8;
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j)
+    for (int j = 0; j < PT; ++j)
         if (ch.valid(j)) store_link(base + (size_t)(ch.k0 + j) * 8, ch.U[j]);
 }
 
@@ -526,7 +535,7 @@ __global__ void __launch_bounds__(256) k_chain_init(ChainArgs a, double sx, doub
 // A chain that runs away (a non-finite drift maximum, norm or loop) keeps its
 // links of the call's start and is advanced no further; its workgroup goes on
 // (every thread takes every barrier) until all of its chains are done.
-template <int B, int T>
+template <int B, int T, int PT>
 __global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
 {
     __shared__ ChainLds<B> s;
@@ -539,13 +548,13 @@ __global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
     if (block_all_true(status != 0, s)) return;  // workgroup-uniform
     int64_t step = exists ? cc->step : 0;
     double bound = exists ? cc->bound : 0.0;
-    Chain ch;
+    Chain<PT> ch;
     chain_load(a, chain, g, ch);
     double sL_re = 0.0, sL_im = 0.0, sd = 0.0, st = 0.0, eps = 0.0, kmax = 0.0, d_pre = 0.0, d = 0.0;
     cxd L = {0.0, 0.0};
     int done = 0;
     for (int i = 0; i < n_steps; ++i) {
-        m2 K[kChainPerThread];
+        m2 K[PT];
         const double km = chain_drift(a, ch, g, s, K);  // chain-uniform
         if (status == 0) {
             kmax = km;
@@ -559,7 +568,7 @@ __global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
         }
         const double se = sqrt(e) * 1.41421356237309504880;  // sqrt(eps) * sqrt(2)
 #pragma unroll
-        for (int j = 0; j < kChainPerThread; ++j) {
+        for (int j = 0; j < PT; ++j) {
             if (!ch.valid(j)) continue;
             double n0, n1, n2, n3;
             const uint32_t k = (uint32_t)(ch.k0 + j);
@@ -628,32 +637,32 @@ __global__ void __launch_bounds__(B) k_chain_run(ChainArgs a, int n_steps)
 }
 
 // the drift of every link (K[chain][k][8]) and K_max (ctrl.kmax)
-template <int B, int T>
+template <int B, int T, int PT>
 __global__ void __launch_bounds__(B) k_chain_drift(ChainArgs a)
 {
     __shared__ ChainLds<B> s;
     const Seg g = make_seg(T);
     const int chain = chain_of(g, B);
-    Chain ch;
+    Chain<PT> ch;
     chain_load(a, chain, g, ch);
-    m2 K[kChainPerThread];
+    m2 K[PT];
     const double kmax = chain_drift(a, ch, g, s, K);
     if (chain >= a.n_chains) return;
     double* base = a.K + (size_t)chain * a.n * 8;
 #pragma unroll
-    for (int j = 0; j < kChainPerThread; ++j)
+    for (int j = 0; j < PT; ++j)
         if (ch.valid(j)) store_link(base + (size_t)(ch.k0 + j) * 8, K[j]);
     if (g.lt == 0) a.ctrl[chain].kmax = kmax;
 }
 
 // n_cool cooling steps of every chain, then L and d into the control block
-template <int B, int T>
+template <int B, int T, int PT>
 __global__ void __launch_bounds__(B) k_chain_cool(ChainArgs a)
 {
     __shared__ ChainLds<B> s;
     const Seg g = make_seg(T);
     const int chain = chain_of(g, B);
-    Chain ch;
+    Chain<PT> ch;
     chain_load(a, chain, g, ch);
     for (int ic = 0; ic < a.n_cool; ++ic) chain_cool_step(a, ch, g, s);
     const double un = chain_unorm(ch, g, s);
@@ -670,13 +679,13 @@ __global__ void __launch_bounds__(B) k_chain_cool(ChainArgs a)
 }
 
 // L and d of every chain into the control block
-template <int B, int T>
+template <int B, int T, int PT>
 __global__ void __launch_bounds__(B) k_chain_measure(ChainArgs a)
 {
     __shared__ ChainLds<B> s;
     const Seg g = make_seg(T);
     const int chain = chain_of(g, B);
-    Chain ch;
+    Chain<PT> ch;
     chain_load(a, chain, g, ch);
     const double un = chain_unorm(ch, g, s);
     const m2 Pt = chain_product(ch, g, s);
@@ -688,41 +697,48 @@ __global__ void __launch_bounds__(B) k_chain_measure(ChainArgs a)
     }
 }
 
-// threads per chain: the smallest power of two T with kChainPerThread T >= n
+// links per thread, and threads per chain: the smallest power of two T with
+// PT T >= n
+int chain_per_thread(int n) { return n <= kChainShortMax ? kChainShortPT : kChainLongPT; }
+
 int chain_threads(int n)
 {
+    const int pt = chain_per_thread(n);
     int T = 1;
-    while (T * kChainPerThread < n) T *= 2;
+    while (T * pt < n) T *= 2;
     return T;
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// launchers: chains of up to 256 links in 64-thread workgroups (64 / T chains
-// each), longer ones in 256-thread workgroups (256 / T chains each)
+// launchers: chains of up to 128 links in 64-thread workgroups (64 / T chains
+// each, two links per thread), longer ones in 256-thread workgroups (256 / T
+// chains each; two links per thread up to 512 links, four above)
 
-#define CHAIN_CASE(KERNEL, TT, ...)                                                                     \
-    case TT: {                                                                                          \
+#define CHAIN_CASE(KERNEL, TT, PTT, ...)                                                                \
+    case TT * 8 + PTT: {                                                                                \
         constexpr int B = TT <= 64 ? 64 : 256;                                                          \
-        hipLaunchKernelGGL((KERNEL<B, TT>), dim3((a.n_chains + B / TT - 1) / (B / TT)), dim3(B), 0, st, \
-                           __VA_ARGS__);                                                                \
+        hipLaunchKernelGGL((KERNEL<B, TT, PTT>), dim3((a.n_chains + B / TT - 1) / (B / TT)), dim3(B), 0,  \
+                           st, __VA_ARGS__);                                                            \
         break;                                                                                          \
     }
 
-// one kernel instance per chain width T (loops over the chain's threads unroll)
+// one kernel instance per chain geometry (T, PT): the loops over the chain's
+// threads and over a thread's links unroll
 #define CHAIN_LAUNCH(KERNEL, ...)                                                                       \
     do {                                                                                                \
-        switch (chain_threads(a.n)) {                                                                   \
-            CHAIN_CASE(KERNEL, 1, __VA_ARGS__)                                                          \
-            CHAIN_CASE(KERNEL, 2, __VA_ARGS__)                                                          \
-            CHAIN_CASE(KERNEL, 4, __VA_ARGS__)                                                          \
-            CHAIN_CASE(KERNEL, 8, __VA_ARGS__)                                                          \
-            CHAIN_CASE(KERNEL, 16, __VA_ARGS__)                                                         \
-            CHAIN_CASE(KERNEL, 32, __VA_ARGS__)                                                         \
-            CHAIN_CASE(KERNEL, 64, __VA_ARGS__)                                                         \
-            CHAIN_CASE(KERNEL, 128, __VA_ARGS__)                                                        \
-            CHAIN_CASE(KERNEL, 256, __VA_ARGS__)                                                        \
+        switch (chain_threads(a.n) * 8 + chain_per_thread(a.n)) {                                       \
+            CHAIN_CASE(KERNEL, 1, 2, __VA_ARGS__)                                                       \
+            CHAIN_CASE(KERNEL, 2, 2, __VA_ARGS__)                                                       \
+            CHAIN_CASE(KERNEL, 4, 2, __VA_ARGS__)                                                       \
+            CHAIN_CASE(KERNEL, 8, 2, __VA_ARGS__)                                                       \
+            CHAIN_CASE(KERNEL, 16, 2, __VA_ARGS__)                                                      \
+            CHAIN_CASE(KERNEL, 32, 2, __VA_ARGS__)                                                      \
+            CHAIN_CASE(KERNEL, 64, 2, __VA_ARGS__)                                                      \
+            CHAIN_CASE(KERNEL, 128, 2, __VA_ARGS__)                                                     \
+            CHAIN_CASE(KERNEL, 256, 2, __VA_ARGS__)                                                     \
+            CHAIN_CASE(KERNEL, 256, 4, __VA_ARGS__)                                                     \
             default: return hipErrorInvalidValue;                                                       \
         }                                                                                               \
     } while (0)

@@ -16,8 +16,11 @@
 namespace clgc {
 
 constexpr int kChainBlock = 256;      // most threads per chain (and per workgroup)
-constexpr int kChainPerThread = 4;    // links per thread
-constexpr int kChainMaxLinks = kChainBlock * kChainPerThread;
+// links per thread: two up to kChainShortMax links (two waves per SIMD), four
+// for longer chains (one wave, fewer threads to scan over)
+constexpr int kChainShortPT = 2, kChainLongPT = 4;
+constexpr int kChainShortMax = kChainBlock * kChainShortPT;
+constexpr int kChainMaxLinks = kChainBlock * kChainLongPT;
 constexpr int kChainObs = 6;          // Re L, Im L, d, eps, kmax, d before cooling
 
 // Philox stream tags of the chain (counter word 3 = tag << 16 | draw)

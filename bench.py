@@ -89,12 +89,15 @@ def algorithmic_cost(kind, V, rs, theta):
         # adj(P) (2 products, 3 adjugates, 2 complex axpys of 9 entries); with
         # the theta term the transported clover adds, per corner d2 and d3, two
         # products, an adjugate and the det(R)^-1 scaling (~122 flops), plus the
-        # staple product R, four insertion products and two scalings.  Per link:
-        # e0 A + B adj(e0) and the traceless part.
-        axpy, scale, transport = 2 * 9 * 8, 2 * 9 * 6, 2 * prod + adj + 122
-        loop = (6 * prod + 3 * adj + 2 * transport + axpy + scale) if theta else (2 * prod + 3 * adj + axpy)
+        # staple product R, the two insertions of Q and the scaling of Q; per
+        # plane the two signs' P_+ - P_- and P'_+ - P'_- (36 flops) meet X0 in
+        # two products after one scaling.  Per link: e0 A + B adj(e0) and the
+        # traceless part.
+        axpy, scl, transport = 2 * 9 * 8, 9 * 6, 2 * prod + adj + 122
+        loop = (4 * prod + 3 * adj + 2 * transport + axpy + scl) if theta else (2 * prod + 3 * adj + axpy)
+        plane = (2 * prod + scl + 36) if theta else 0
         byt = L * (mat + mat) + (V * 6 * mat if theta else 0)  # links + K out (+ F in)
-        return {"bytes": byt, "flops": L * (6 * loop + 2 * prod + adj)}
+        return {"bytes": byt, "flops": L * (6 * loop + 3 * plane + 2 * prod + adj)}
     if kind == "update":
         return {"bytes": L * 3 * mat, "flops": L * (3 * prod + 600)}
     if kind == "clover":

@@ -429,14 +429,13 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
             const int Pl = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
             const int fo = dual_plane(Pl) * ra.V;
             // The dual clover matrices at d1 = x + mu and at x do not depend on
-            // the sign: FP64 loads them once per plane (its overflow registers
-            // hold them); FP32 would spill and reloads them per sign.
+            // the sign.  FP64 loads X1 once per plane (its overflow registers
+            // hold it) and, since cts changes sign with s, multiplies X0 once
+            // per plane: sum_s cts_s P_s X0 = cts_+ (P_+ - P_-) X0, and the same
+            // for X0 P'_s.  FP32 would spill and takes both per sign.
             constexpr bool kHoist = sizeof(T) == 8;
-            mat3<T> X1 = m_zero<T>(), X0 = m_zero<T>();
-            if (kHoist && th) {
-                X1 = load_mat(Fb, fo + link_off(ra, 0, d1), fs);
-                X0 = load_mat(Fb, fo + p * ra.Vh + h, fs);
-            }
+            mat3<T> X1 = m_zero<T>(), Dp = m_zero<T>(), Da = m_zero<T>();
+            if (kHoist && th) X1 = load_mat(Fb, fo + link_off(ra, 0, d1), fs);
             // unrolled over the sign: a compile-time s selects the raw link or its
             // adjugate
 #pragma unroll
@@ -475,10 +474,27 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                     Q = m_scale(Q, cts);
                     m_mac(A, Q, Pm);
                     m_mac(B, Pa, Q);
-                    const mat3<T> X0s = m_scale(kHoist ? X0 : load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
-                    m_mac(A, Pm, X0s);
-                    m_mac(B, X0s, Pa);
+                    if constexpr (kHoist) {
+                        if (s > 0) {
+                            Dp = Pm;
+                            Da = Pa;
+                        } else {
+                            Dp = Dp - Pm;
+                            Da = Da - Pa;
+                        }
+                    } else {
+                        const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
+                        m_mac(A, Pm, X0s);
+                        m_mac(B, X0s, Pa);
+                    }
                 }
+            }
+            if (kHoist && th) {
+                __builtin_amdgcn_sched_barrier(0);
+                const T sig = T((nu > mu ? 1 : -1) * dual_sign(Pl));
+                const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cx<T>{sig * ct.re, sig * ct.im});
+                m_mac(A, Dp, X0s);
+                m_mac(B, X0s, Da);
             }
         }
         if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);

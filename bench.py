@@ -86,15 +86,18 @@ def algorithmic_cost(kind, V, rs, theta):
                 "flops": L * 2 * hprod + (V // 2) * (8 * 54 + hexp)}
     if kind == "drift":
         # one walk per loop along the staple P = e1 e2 e3: Wilson part P and
-        # adj(P) (2 products, 3 adjugates, 2 complex axpys of 9 entries); with
-        # the theta term the transported clover adds, per corner d2 and d3, two
-        # products, an adjugate and the det(R)^-1 scaling (~122 flops), plus the
-        # staple product R, the two insertions of Q and the scaling of Q; per
-        # plane the two signs' P_+ - P_- and P'_+ - P'_- (36 flops) meet X0 in
-        # two products after one scaling.  Per link: e0 A + B adj(e0) and the
+        # adj(P) (2 products, 3 adjugates, 2 complex axpys of 9 entries).  With
+        # the theta term: the transported clover X1 + e1 (X2 + e2 X3 e2^-1) e1^-1
+        # (four products, two determinant reciprocals with their scalings and
+        # additions, 2 x (26 + 54 + 18) flops), the staple products R = e1 e2
+        # and P, the two insertions of Q and the scaling of Q; adjugates of the
+        # two raw links, of P and, on every other loop, of e3.  Per plane the
+        # two signs' P_+ - P_- and P'_+ - P'_- (36 flops) meet X0 in two
+        # products after one scaling.  Per link: e0 A + B adj(e0) and the
         # traceless part.
-        axpy, scl, transport = 2 * 9 * 8, 9 * 6, 2 * prod + adj + 122
-        loop = (4 * prod + 3 * adj + 2 * transport + axpy + scl) if theta else (2 * prod + 3 * adj + axpy)
+        axpy, scl = 2 * 9 * 8, 9 * 6
+        loop = ((8 * prod + (7 * adj) // 2 + 2 * (26 + scl + 18) + axpy + scl) if theta
+                else (2 * prod + 3 * adj + axpy))
         plane = (2 * prod + scl + 36) if theta else 0
         byt = L * (mat + mat) + (V * 6 * mat if theta else 0)  # links + K out (+ F in)
         return {"bytes": byt, "flops": L * (6 * loop + 3 * plane + 2 * prod + adj)}

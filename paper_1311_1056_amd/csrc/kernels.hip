@@ -369,29 +369,19 @@ __global__ void __launch_bounds__(kBlock, 2) k_clover(const KArgs ka,
 // from d1 to the corners and the transported clover Q = sum_k R_k X_k R_k^-1,
 //   I = Q P + P X0,    J = X0 P' + P' Q,
 // so one walk along the staple gives both chains.  Inverses are adjugates
-// (the inverse on SL(3,C)); adj(AB) = adj(B) adj(A) makes P' = adj(P) exact,
-// and R_k^-1 = adj(R_k)/det(R_k) keeps both identities exact for any links.
-// One lane per link loads each of a loop's seven matrices once.
+// (the inverse on SL(3,C)); adj(AB) = adj(B) adj(A) makes P' = adj(P) exact.
+// Q is summed nested, X1 + e1 (X2 + e2 X3 e2^-1) e1^-1, with e1^-1 and e2^-1
+// from the raw links' adjugates and determinants, which keeps both identities
+// exact for any links.  One lane per link loads each of a loop's seven
+// matrices once.
 
-// Q += R X R^-1 with R^-1 = adj(R) / det(R)
+// 1 / det M from the first row of M and the first column of adj(M)
 template <typename T>
-__device__ __forceinline__ void add_transported(mat3<T>& Q, const mat3<T>& R, const mat3<T>& X)
+__device__ __forceinline__ cx<T> inv_det(const mat3<T>& M, const mat3<T>& Ma)
 {
-    const mat3<T> Ra = m_adj(R);
-    // det R from the first row of R and the first column of adj(R)
-    const cx<T> d = cfma(R.e[0][2], Ra.e[2][0], cfma(R.e[0][1], Ra.e[1][0], R.e[0][0] * Ra.e[0][0]));
+    const cx<T> d = cfma(M.e[0][2], Ma.e[2][0], cfma(M.e[0][1], Ma.e[1][0], M.e[0][0] * Ma.e[0][0]));
     const T r = T(1) / fma(d.re, d.re, d.im * d.im);
-    const cx<T> di = {d.re * r, -d.im * r};
-    const mat3<T> RX = R * X;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cx<T> t = RX.e[i][0] * Ra.e[0][j];
-            t = cfma(RX.e[i][1], Ra.e[1][j], t);
-            t = cfma(RX.e[i][2], Ra.e[2][j], t);
-            Q.e[i][j] = cfma(t, di, Q.e[i][j]);
-        }
+    return {d.re * r, -d.im * r};
 }
 
 // FP64 with the theta term runs one wave per SIMD: its walk needs ~440
@@ -447,9 +437,10 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                 const Site d3 = site_move(ra, x, nu, s);
                 const Site d2 = site_move(ra, d1, nu, s);
                 // e1 = U_nu(d1) (s>0) or U_nu(d2)^-1, e2 = U_mu(d3)^-1, e3 = U_nu(x)^-1 (s>0) or U_nu(d3)
-                mat3<T> e1 = load_mat(Ub, link_off(ra, nu, s > 0 ? d1 : d2), us);
-                if (s < 0) e1 = m_adj(e1);
+                const int oa = link_off(ra, nu, s > 0 ? d1 : d2);
                 if (!th) {
+                    const mat3<T> ua = load_mat(Ub, oa, us);
+                    const mat3<T> e1 = s > 0 ? ua : m_adj(ua);
                     mat3<T> Pm = e1 * m_adj(load_mat(Ub, link_off(ra, mu, d3), us));
                     mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
                     if (s > 0) e3 = m_adj(e3);
@@ -459,11 +450,30 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                 } else {
                     const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(Pl));
                     const cx<T> cts = {sig * ct.re, sig * ct.im};
-                    mat3<T> Q = kHoist ? X1 : load_mat(Fb, fo + link_off(ra, 0, d1), fs);
-                    add_transported(Q, e1, load_mat(Fb, fo + link_off(ra, 0, d2), fs));
+                    // Q = X1 + e1 X2 e1^-1 + (e1 e2) X3 (e1 e2)^-1 = X1 + e1 Y e1^-1 with
+                    // Y = X2 + e2 X3 e2^-1.  Inverses from the raw links: e2 =
+                    // adj(ub) has e2^-1 = ub / det ub, and e1^-1 is adj(ua) / det ua
+                    // (s > 0) or ua / det ua (s < 0, e1 = adj(ua)); exact for any
+                    // links, not only det U = 1.
+                    const mat3<T> ub = load_mat(Ub, link_off(ra, mu, d3), us);
+                    const mat3<T> e2 = m_adj(ub);
+                    mat3<T> Y = (e2 * load_mat(Fb, fo + link_off(ra, 0, d3), fs)) * ub;
+                    Y = m_scale(Y, inv_det(ub, e2)) + load_mat(Fb, fo + link_off(ra, 0, d2), fs);
                     if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
-                    const mat3<T> R = e1 * m_adj(load_mat(Ub, link_off(ra, mu, d3), us));
-                    add_transported(Q, R, load_mat(Fb, fo + link_off(ra, 0, d3), fs));
+                    const mat3<T> ua = load_mat(Ub, oa, us);
+                    const mat3<T> ua_adj = m_adj(ua);
+                    const cx<T> ida = inv_det(ua, ua_adj);
+                    mat3<T> e1, e1i;
+                    if (s > 0) {
+                        e1 = ua;
+                        e1i = ua_adj;
+                    } else {
+                        e1 = ua_adj;
+                        e1i = ua;
+                    }
+                    const mat3<T> R = e1 * e2;
+                    mat3<T> Q = m_scale((e1 * Y) * e1i, ida) +
+                                (kHoist ? X1 : load_mat(Fb, fo + link_off(ra, 0, d1), fs));
                     if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
                     mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
                     if (s > 0) e3 = m_adj(e3);

@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "CL+cooling link-updates/s at 16^4, FP64 vs mixed; served p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VALU_FP64_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
-VALU_FP32_TFLOPS = 78.6        # same rate: packed FP32 instructions are disabled in this build
+VALU_FP32_TFLOPS = 78.6        # same rate: the library is compiled without packed FP32 instructions
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1311_1056_amd", "csrc", "kernels.hip")
 
@@ -66,7 +66,7 @@ def kernel_src_hash():
 
 
 def algorithmic_cost(kind, V, rs, theta):
-    """Algorithmic bytes and flops of one launch (kernels section).
+    """Algorithmic bytes and flops of one launch.
 
     Bytes: every field element the kernel must touch, read or written once.
     Flops: 3x3 complex product = 108 FMA = 216 flops, adjugate = 126 flops,
@@ -632,7 +632,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
               "independent runs shard across GPUs with no exchange, so the per-GPU figure is the N=1 line",
               file=sys.stderr, flush=True)
         sys.exit(2)

@@ -35,7 +35,8 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
 
 // Two standard normals from one block of four words: two 53-bit uniforms in
 // (0, 1) from (w0, w1) and (w2, w3), then Box-Muller.  The uniforms are built
-// exactly in double; the transform runs in the working precision R.
+// exactly in double; the transform runs in the working precision R (in float,
+// ln u on the upper half goes through log1p(u - 1)).
 template <typename R>
 __device__ __forceinline__ void normal_pair(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
                                             uint32_t c3, R& n0, R& n1)
@@ -43,7 +44,16 @@ __device__ __forceinline__ void normal_pair(uint64_t seed, uint32_t c0, uint32_t
     const u32x4 w = philox4x32_10(u32x4{c0, c1, c2, c3}, (uint32_t)seed, (uint32_t)(seed >> 32));
     const double uA = fma((double)(w.x >> 5), 67108864.0, (double)(w.y >> 6) + 0.5) * 0x1p-53;
     const double uB = fma((double)(w.z >> 5), 67108864.0, (double)(w.w >> 6) + 0.5) * 0x1p-53;
-    const R r = sqrt(R(-2) * log(R(uA)));
+    R r;
+    if constexpr (sizeof(R) == sizeof(float)) {
+        // rounding u to float near u = 1 would dominate ln u (its spacing there,
+        // 6e-8, is comparable to 1 - u); u - 1 is exact in double, so log1p of
+        // it keeps ln u to float accuracy on the upper half
+        const float l = uA < 0.5 ? logf((float)uA) : log1pf((float)(uA - 1.0));
+        r = sqrtf(-2.0f * l);
+    } else {
+        r = sqrt(R(-2) * log(R(uA)));
+    }
     R s, c;
     if constexpr (sizeof(R) == sizeof(float)) sincospif(R(2) * R(uB), &s, &c);
     else sincospi(R(2) * R(uB), &s, &c);

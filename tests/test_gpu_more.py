@@ -144,6 +144,37 @@ def test_large_lattice_sampled_drift(cl, orc, dims):
         lat.close()
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(24, 24, 24, 24), (32, 32, 32, 32)])
+def test_large_lattice_mixed_against_fp64_step(cl, dims):
+    """24^4 and 32^4, theta 1, seed 4: one CL step (adaptive eps) and 10 D_1
+    cooling steps on the mixed and the FP64 path from identical links and the
+    same Philox words.  Per-step link error <= 1e-5 relative, plaquette and d
+    within 1e-6 of max(1, |value|), Q within 1e-5.  The FP64 path is the one pinned to the
+    oracle at smaller sizes and on sampled links here."""
+    mx = cl.Lattice(dims, 6.0, 1.0, cl.CL_MIXED, seed=4)
+    mx.init(True, 0.3, 0.05)
+    U = mx.get_links()  # FP32-representable: both paths start from these
+    fp = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=4)
+    fp.set_links(U)
+    del U
+    for lat in (mx, fp):
+        lat.run_steps(1, 1e-2, True, 10, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    a, b = mx.measure(), fp.measure()
+    err = relerr(mx.get_links(), fp.get_links())
+    say(f"{dims}: mixed vs FP64 one step, link rel err {err:.2e}, eps {a['eps']:.6e} / {b['eps']:.6e}")
+    assert err <= 1e-5
+    assert abs(a["eps"] - b["eps"]) <= 1e-5 * b["eps"]
+    for k in ("plaq", "d"):
+        assert abs(a[k] - b[k]) <= 1e-6 * max(1.0, abs(b[k])), (k, a[k], b[k])
+    # the mixed clover is formed in FP32 as L - L^-1 of near-identity loops, so
+    # each site's charge density carries ~1e-6 relative rounding, and Q sums V
+    # of them (1.3e-6 relative measured at 32^4)
+    assert abs(a["q"] - b["q"]) <= 1e-5 * max(1.0, abs(b["q"])), (a["q"], b["q"])
+    mx.close()
+    fp.close()
+
+
 def test_minimum_and_ragged_lattices(cl, orc):
     """2^4 (every neighbour wraps) and extents with a ragged last block."""
     for dims in [(2, 2, 2, 2), (2, 6, 4, 10), (6, 2, 2, 2)]:

@@ -932,6 +932,160 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
     CLGC_END_BLOCKS
 }
 
+// The same cooling step for a lattice whose blocks loop over several chunks
+// (more than kMaxCoolBlocks chunks): each wavefront issues the next chunk's
+// loads before it works on the current one, so HBM keeps streaming while the
+// chunk's arithmetic runs.  The run state is read once per wavefront.  Same
+// products in the same order as k_cool_omega / k_cool_apply: the results are
+// bitwise equal.
+
+// lane (h, mu) of chunk c: U_mu(x) and U_mu(x - mu) of even site h
+template <typename T>
+__device__ __forceinline__ void omega_loads(const RunArgs& ra, int c, int& h, bool& lok, mat3<T>& Af, mat3<T>& Ab)
+{
+    const int t = c * kBlock + (int)threadIdx.x;
+    const int mu = t & 3;
+    h = t >> 2;
+    lok = h < ra.Vh;
+    if (lok) {
+        const Site x = site_coords(ra, 0, h);
+        const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
+        Af = load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V);
+        Ab = load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V);
+    }
+}
+
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int iter)
+{
+    CLGC_FOR_BLOCKS(KIND_COOL)
+    Ctrl* cr = ra.ctrl;
+    if (iter < ra.n_cool) {
+        const int nch = cool_chunks_total(ra.V);
+        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
+        const int c0 = lb * per, c1 = min((lb + 1) * per, nch);
+        const int mu = (int)threadIdx.x & 3;
+        int h = 0;
+        bool lok = false;
+        mat3<T> Af, Ab;
+        if (c0 < c1) omega_loads(ra, c0, h, lok, Af, Ab);
+        // the run state, as in k_cool_omega
+        const bool ok = cr->status == ST_OK;
+        const double un = iter == 0 ? cr->unorm : wave_cool_sum(ra);
+        const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
+        const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
+                                             : (ra.mode == 2 ? ra.alpha / d2 : ra.alpha);
+        if (ok && lb == 0 && c0 < c1 && threadIdx.x == 0) {
+            cr->alpha_cur = alpha_ad;
+            cr->unorm = un;
+            if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
+            if (iter < kMaxCoolHist) {
+                cr->hist_alpha[iter] = alpha_ad;
+                cr->hist_un[iter] = un;
+                cr->hist_n = iter + 1;
+            }
+        }
+        const T coef = T(-4.0 * ra.eps_c * alpha_ad);
+        for (int c = c0; c < c1; ++c) {
+            int hn = 0;
+            bool lokn = false;
+            mat3<T> Nf, Nb;
+            if (c + 1 < c1) omega_loads(ra, c + 1, hn, lokn, Nf, Nb);
+            herm3<T> G = h_zero<T>();
+            if (lok) {
+                h_add_uudag(G, Af);
+                h_sub_udagu(G, Ab);
+            }
+            herm3<T> E, Ei;
+            site_omega(G, coef, E, Ei);
+            if (ok && lok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
+            h = hn;
+            lok = lokn;
+            Af = Nf;
+            Ab = Nb;
+        }
+    }
+    CLGC_END_BLOCKS
+}
+
+// lane (h, mu) of chunk c: U_mu(y), U_mu(y - mu) of odd site h and the even
+// transforms they take (Omega^-1 of y + mu, Omega of y - mu)
+template <typename T>
+struct ApplyIn {
+    mat3<T> Uf, Ub;
+    herm3<T> Eif, Eb;
+    int of, ob;
+    bool lok;
+};
+
+template <typename T>
+__device__ __forceinline__ void apply_loads(const RunArgs& ra, int c, ApplyIn<T>& in)
+{
+    const int t = c * kBlock + (int)threadIdx.x;
+    const int h = t >> 2, mu = t & 3;
+    in.lok = h < ra.Vh;
+    if (in.lok) {
+        const Site y = site_coords(ra, 1, h);
+        const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
+        in.of = (mu * 2 + 1) * ra.Vh + h;
+        in.ob = link_off(ra, mu, yb);
+        const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
+        const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
+        in.Uf = load_mat(Uc, in.of, 4 * ra.V);
+        in.Eif = load_herm<T>(om, site_half(ra, yf), ra.Vh, 9);
+        in.Eb = load_herm<T>(om, site_half(ra, yb), ra.Vh, 0);
+        in.Ub = load_mat(Uc, in.ob, 4 * ra.V);
+    }
+}
+
+template <typename T, bool FAST>
+__global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int iter)
+{
+    __shared__ double lds[8];
+    CLGC_FOR_BLOCKS(KIND_COOL)
+    Ctrl* cr = ra.ctrl;
+    if (iter < ra.n_cool) {
+        const int nch = cool_chunks_total(ra.V);
+        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
+        const int c0 = lb * per, c1 = min((lb + 1) * per, nch);
+        ApplyIn<T> cur;
+        cur.lok = false;
+        if (c0 < c1) apply_loads(ra, c0, cur);
+        // (no kernel writes the status during this launch)
+        const bool ok = cr->status == ST_OK;
+        const T coef = T(-4.0 * ra.eps_c * cr->alpha_cur);
+        double un = 0.0;
+        for (int c = c0; c < c1; ++c) {
+            ApplyIn<T> nxt;
+            nxt.lok = false;
+            if (c + 1 < c1) apply_loads(ra, c + 1, nxt);
+            herm3<T> G = h_zero<T>();
+            mat3<T> Uf, Ub;
+            if (cur.lok) {
+                Uf = mul_h(cur.Uf, cur.Eif);
+                Ub = h_mul(cur.Eb, cur.Ub);
+                h_add_uudag(G, Uf);
+                h_sub_udagu(G, Ub);
+            }
+            herm3<T> E, Ei;
+            site_omega(G, coef, E, Ei);
+            if (ok && cur.lok) {
+                const mat3<T> Nf = h_mul(E, Uf);
+                const mat3<T> Nb = mul_h(Ub, Ei);
+                cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
+                store_mat(Uw, cur.of, 4 * ra.V, Nf);
+                store_mat(Uw, cur.ob, 4 * ra.V, Nb);
+                un += (double)m_norm2(Nf) + (double)m_norm2(Nb);
+            }
+            cur = nxt;
+        }
+        double v[1] = {un};
+        block_reduce<1>(v, lds);
+        if (ok && threadIdx.x == 0) ra.cpart[lb] = v[0];
+    }
+    CLGC_END_BLOCKS
+}
+
 // D_2 = mean over (a, x) of |f_ax| on the configuration entering a cooling
 // step, f_ax = 2 Tr(lambda_a G_x).  Two lanes per site (directions 0, 1 and
 // 2, 3, joined by one shuffle), on the cooling kernels' logical blocks: the
@@ -1263,6 +1417,19 @@ hipError_t launch_update(const Launch& L, int prec)
 
 hipError_t launch_cool(const Launch& L, int prec, int phase, int iter)
 {
+    // a single lattice whose cooling blocks loop over several chunks takes the
+    // prefetching kernels (a batch keeps the plain ones: its runs are mostly
+    // small, and the prefetching ones hold more registers)
+    if (L.fast && cool_chunks_total(L.one.V) > kMaxCoolBlocks) {
+        if (prec) {
+            if (phase) CLGC_LAUNCH((k_cool_apply_pf<float, FAST_>), KIND_COOL, iter);
+            else CLGC_LAUNCH((k_cool_omega_pf<float, FAST_>), KIND_COOL, iter);
+        } else {
+            if (phase) CLGC_LAUNCH((k_cool_apply_pf<double, FAST_>), KIND_COOL, iter);
+            else CLGC_LAUNCH((k_cool_omega_pf<double, FAST_>), KIND_COOL, iter);
+        }
+        return hipGetLastError();
+    }
     if (prec) {
         if (phase) CLGC_LAUNCH((k_cool_apply<float, FAST_>), KIND_COOL, iter);
         else CLGC_LAUNCH((k_cool_omega<float, FAST_>), KIND_COOL, iter);

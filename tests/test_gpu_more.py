@@ -332,19 +332,21 @@ def test_real_langevin_and_cooling_invariants(cl):
     lat.close()
 
 
-def test_d2_cooling_with_chunked_gradient_pass(cl, orc):
-    """D_2 cooling on 24^3 x 16: the gradient-norm pass then has more chunks
-    of sites than logical blocks (864 over 512), so its blocks loop; the next
-    omega kernel's wavefronts sum its partials.  Links and the alpha / norm
-    history against the oracle (oracle start, not the GPU's)."""
-    dims = (24, 24, 24, 16)
-    say("D2 cooling 24^3x16")
+@pytest.mark.parametrize("dims,mode", [((24, 24, 24, 16), 2), ((18, 18, 18, 22), 1), ((18, 18, 18, 22), 0)])
+def test_d2_cooling_with_chunked_gradient_pass(cl, orc, dims, mode):
+    """Cooling on lattices with more chunks of sites than cooling blocks (24^3 x
+    16: 1728 over 512; 18^3 x 22: 1003, the last one ragged), so every block
+    loops and the prefetching cooling kernels run; with D_2 the gradient-norm
+    pass loops too and the next omega kernel's wavefronts sum its partials.
+    Links and the alpha / norm history against the oracle (oracle start, not
+    the GPU's)."""
+    say("chunked cooling", dims, mode)
     U = orc.init_links(dims, 7, 0.3, 0.1)
     lat = cl.Lattice(dims, 6.0, 0.0, cl.CL_FP64)
     lat.set_links(U)
-    lat.gauge_cool(2, 1e-2, 1.0, cl.CL_ALPHA_GRAD)
+    lat.gauge_cool(2, 1e-2, 1.0, mode)
     W = U.copy()
-    un, al = orc.gauge_cool(dims, W, 2, 1e-2, 1.0, 2)
+    un, al = orc.gauge_cool(dims, W, 2, 1e-2, 1.0, mode)
     assert relerr(lat.get_links(), W) < 1e-12
     hu, ha = lat.cool_history()
     np.testing.assert_allclose(hu, un, rtol=1e-13)

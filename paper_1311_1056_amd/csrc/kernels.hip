@@ -313,23 +313,34 @@ __global__ void __launch_bounds__(kBlock, 2) k_clover(const KArgs ka,
         const Site xmnpm = site_move(ra, xmn, mu, +1);
         mat3<T> F, L;
         if constexpr (sizeof(T) == 8) {
-            // FP64: each leaf loads its own four links (repeats hit in cache) and
-            // the scheduling barriers keep the next leaf's loads from being
-            // hoisted, which holds two waves per SIMD without spilling
+            // FP64: the scheduling barriers keep the next leaf's loads from being
+            // hoisted, which holds two waves per SIMD without spilling; a link
+            // shared with the next leaf stays in registers (U_nu(x), U_mu(x-mu),
+            // U_nu(x-nu)), the one shared by the first and the last leaf,
+            // U_mu(x), is loaded again (a cache hit)
             // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
-            L = (ldU<T>(ra, mu, x) * ldU<T>(ra, nu, xpm)) * m_adj(ldU<T>(ra, nu, x) * ldU<T>(ra, mu, xpn));
+            mat3<T> S = ldU<T>(ra, nu, x);
+            L = (ldU<T>(ra, mu, x) * ldU<T>(ra, nu, xpm)) * m_adj(S * ldU<T>(ra, mu, xpn));
             F = L - m_adj(L);
             __builtin_amdgcn_sched_barrier(0);
             // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
-            L = ldU<T>(ra, nu, x) * (m_adj(ldU<T>(ra, nu, xmm) * ldU<T>(ra, mu, xmmpn)) * ldU<T>(ra, mu, xmm));
+            {
+                const mat3<T> Umm = ldU<T>(ra, mu, xmm);
+                L = S * (m_adj(ldU<T>(ra, nu, xmm) * ldU<T>(ra, mu, xmmpn)) * Umm);
+                S = Umm;
+            }
             F = F + (L - m_adj(L));
             __builtin_amdgcn_sched_barrier(0);
             // [U_nu(x-mu-nu) U_mu(x-mu)]^{-1} U_mu(x-mu-nu) U_nu(x-nu)
-            L = m_adj(ldU<T>(ra, nu, xmmmn) * ldU<T>(ra, mu, xmm)) * (ldU<T>(ra, mu, xmmmn) * ldU<T>(ra, nu, xmn));
+            {
+                const mat3<T> Unn = ldU<T>(ra, nu, xmn);
+                L = m_adj(ldU<T>(ra, nu, xmmmn) * S) * (ldU<T>(ra, mu, xmmmn) * Unn);
+                S = Unn;
+            }
             F = F + (L - m_adj(L));
             __builtin_amdgcn_sched_barrier(0);
             // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
-            L = m_adj(ldU<T>(ra, nu, xmn)) * ((ldU<T>(ra, mu, xmn) * ldU<T>(ra, nu, xmnpm)) * m_adj(ldU<T>(ra, mu, x)));
+            L = m_adj(S) * ((ldU<T>(ra, mu, xmn) * ldU<T>(ra, nu, xmnpm)) * m_adj(ldU<T>(ra, mu, x)));
             F = F + (L - m_adj(L));
         } else {
             const mat3<T> Umx = ldU<T>(ra, mu, x), Unx = ldU<T>(ra, nu, x);

@@ -624,13 +624,13 @@ __device__ __forceinline__ T quad_sum(T v)
 
 
 // real Horner series for exp of a Hermitian traceless matrix (the Hermitian
-// counterpart of ch_exp_coeffs: s, t and the coefficients are real)
-template <typename T>
+// counterpart of ch_exp_coeffs: s, t and the coefficients are real), N terms
+template <typename T, int N>
 __device__ __forceinline__ void ch_exp_coeffs_real(T s, T t, T& f0, T& f1, T& f2)
 {
     T x = T(1), y = T(0), z = T(0);
 #pragma unroll
-    for (int n = exp_terms<T>::n; n >= 1; --n) {
+    for (int n = N; n >= 1; --n) {
         const T inv = T(1) / T(n);
         const T nx = t * z;
         const T ny = fma(s, z, x);
@@ -700,8 +700,18 @@ __device__ __forceinline__ void herm_exp_pair(herm3<T> A, herm3<T>& E, herm3<T>&
     const T t = A.d0 * A.d1 * A.d2 + T(2) * w.re - A.d0 * norm2(A.u12) - A.d1 * norm2(A.u02) -
                 A.d2 * norm2(A.u01);
     T f0, f1, f2, g0, g1, g2;
-    ch_exp_coeffs_real(s, t, f0, f1, f2);
-    ch_exp_coeffs_real(s, -t, g0, g1, g2);
+    // The series needs exp_terms terms for |A|_F <= 1; a cooling step's A is
+    // usually far smaller, and for |A|_F <= 1/8 the terms after the first 10
+    // (FP64; 6 in FP32) add at most 3e-18 (1e-10) relative.  The choice is
+    // taken per wavefront, so the loop stays uniform.
+    constexpr int kShort = sizeof(T) == 8 ? 10 : 6;
+    if (__all(fro2 * ldexp(T(1), -2 * k) <= T(1.0 / 64.0))) {
+        ch_exp_coeffs_real<T, kShort>(s, t, f0, f1, f2);
+        ch_exp_coeffs_real<T, kShort>(s, -t, g0, g1, g2);
+    } else {
+        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, t, f0, f1, f2);
+        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, -t, g0, g1, g2);
+    }
     E = h_poly(f0, f1, f2, A, A2);
     Ei = h_poly(g0, -g1, g2, A, A2);
     for (int i = 0; i < k; ++i) {

@@ -437,6 +437,10 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
             constexpr bool kHoist = sizeof(T) == 8;
             mat3<T> X1 = m_zero<T>(), Dp = m_zero<T>(), Da = m_zero<T>();
             if (kHoist && th) X1 = load_mat(Fb, fo + link_off(ra, 0, d1), fs);
+            // FP64: the s = -1 walk's first two matrices, loaded while the s = +1
+            // walk finishes (one wave per SIMD leaves no other wave to cover
+            // their latency)
+            mat3<T> ubN = m_zero<T>(), X3N = m_zero<T>();
             // unrolled over the sign: a compile-time s selects the raw link or its
             // adjugate
 #pragma unroll
@@ -466,12 +470,25 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                     // adj(ub) has e2^-1 = ub / det ub, and e1^-1 is adj(ua) / det ua
                     // (s > 0) or ua / det ua (s < 0, e1 = adj(ua)); exact for any
                     // links, not only det U = 1.
-                    const mat3<T> ub = load_mat(Ub, link_off(ra, mu, d3), us);
+                    mat3<T> ub, X3;
+                    if (kHoist && si == 1) {
+                        ub = ubN;
+                        X3 = X3N;
+                    } else {
+                        ub = load_mat(Ub, link_off(ra, mu, d3), us);
+                        X3 = load_mat(Fb, fo + link_off(ra, 0, d3), fs);
+                    }
+                    // (FP64: the next stage's link is requested with this one's)
+                    mat3<T> ua;
+                    if constexpr (kHoist) ua = load_mat(Ub, oa, us);
                     const mat3<T> e2 = m_adj(ub);
-                    mat3<T> Y = (e2 * load_mat(Fb, fo + link_off(ra, 0, d3), fs)) * ub;
+                    mat3<T> Y = (e2 * X3) * ub;
                     Y = m_scale(Y, inv_det(ub, e2)) + load_mat(Fb, fo + link_off(ra, 0, d2), fs);
                     if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
-                    const mat3<T> ua = load_mat(Ub, oa, us);
+                    if constexpr (!kHoist) ua = load_mat(Ub, oa, us);
+                    const int o3 = link_off(ra, nu, s > 0 ? x : d3);
+                    mat3<T> e3;
+                    if constexpr (kHoist) e3 = load_mat(Ub, o3, us);
                     const mat3<T> ua_adj = m_adj(ua);
                     const cx<T> ida = inv_det(ua, ua_adj);
                     mat3<T> e1, e1i;
@@ -486,7 +503,12 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                     mat3<T> Q = m_scale((e1 * Y) * e1i, ida) +
                                 (kHoist ? X1 : load_mat(Fb, fo + link_off(ra, 0, d1), fs));
                     if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
-                    mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
+                    if constexpr (!kHoist) e3 = load_mat(Ub, o3, us);
+                    if (kHoist && si == 0) {
+                        const Site d3m = site_move(ra, x, nu, -1);
+                        ubN = load_mat(Ub, link_off(ra, mu, d3m), us);
+                        X3N = load_mat(Fb, fo + link_off(ra, 0, d3m), fs);
+                    }
                     if (s > 0) e3 = m_adj(e3);
                     const mat3<T> Pm = R * e3;
                     const mat3<T> Pa = m_adj(Pm);

@@ -343,8 +343,16 @@ def large_lattice(args):
     a = with_args(args, dims="32,32,32,32", steps=5, warmup=2)
     res = run_gpu(a, "fp64")
     rf, kernels, rfs = roofline(res, "fp64", args.theta)
-    return {"lattice": "32x32x32x32", "value": round(res["value"], 1), "unit": "link-updates/s",
-            "ms_per_step": round(res["ms_per_step"], 4), "steps": a.steps, "roofline": rf, "rooflines": rfs}
+    out = {"lattice": "32x32x32x32", "value": round(res["value"], 1), "unit": "link-updates/s",
+           "ms_per_step": round(res["ms_per_step"], 4), "steps": a.steps, "roofline": rf, "rooflines": rfs}
+    # one GPU's share of a 32^4 lattice split in two along x3 (the kernels at
+    # that shape, periodic here; the halo exchange of a real split is not built)
+    b = with_args(args, dims="32,32,32,16", steps=10, warmup=2)
+    rb = run_gpu(b, "fp64")
+    rfb, _, _ = roofline(rb, "fp64", args.theta)
+    out["half_share_32x32x32x16"] = {"value": round(rb["value"], 1), "unit": "link-updates/s",
+                                     "ms_per_step": round(rb["ms_per_step"], 4), "steps": b.steps, "roofline": rfb}
+    return out
 
 
 def theta_points(args):

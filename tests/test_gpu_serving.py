@@ -106,3 +106,21 @@ def test_runaway_run_is_retired_alone(cl):
         ref = alone(cl, r)
         assert close(res[i]["obs"]["plaq"], ref["plaq"], r["prec"])
     srv.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_large_run_served_equals_alone_bitwise(cl, prec):
+    """A 24^3 x 16 run has more cooling chunks than cooling blocks: alone it
+    takes the prefetching cooling kernels, in the server's batched launch the
+    plain ones.  Both evaluate the same products in the same order, so the
+    observables agree to the last bit."""
+    r = dict(dims=(24, 24, 24, 16), beta=6.0, theta=1.0, prec=prec, seed=107, n_steps=2, eps0=1e-2, n_cool=3,
+             mode=1)
+    srv = cl.Server(2048 << 20)
+    submit(srv, r, 0)
+    res = drain(srv)
+    assert len(res) == 1 and res[0]["status"] == 0
+    ref = alone(cl, r)
+    for k in ("plaq", "q", "d", "eps"):
+        assert res[0]["obs"][k] == ref[k], (k, res[0]["obs"][k], ref[k])
+    srv.close()

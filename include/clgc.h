@@ -275,7 +275,8 @@ typedef struct {
 } cl_chain_obs;
 
 /* Device bytes for the chains, their control blocks and obs_cap steps of record.
- * CL_EINVAL: n_links outside 1..1024, n_chains < 1, obs_cap < 0, beta not finite. */
+ * CL_EINVAL: n_links outside 1..1024, n_chains outside 1..2^24, obs_cap < 0, beta not
+ * finite. */
 cl_status cl_chain_bytes(const cl_chain_desc* desc, size_t* device_bytes);
 /* dev_buf: caller-owned, at least cl_chain_bytes, 256-byte aligned; the stream is
  * the caller's.  The chains start at the identity (a cold start). */

@@ -47,3 +47,28 @@ def test_descriptor_validation_without_gpu():
         cl.cl_lattice_bytes(cl.make_desc((4, 4, 4, 4), -1.0))
     with pytest.raises(cl.ClError):
         cl.cl_lattice_bytes(cl.make_desc((4, 4, 4, 4), 6.0, precision=7))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libclgc.so not built")
+def test_maximum_sizes_without_gpu():
+    """Every field must stay below 4 GiB (one 32-bit buffer resource): the
+    clover field, 864 V bytes in FP64 and 432 V in mixed precision, sets the
+    largest lattice, 46^4 (FP64) and 56^4 (mixed); the next even sizes are
+    refused.  Chains: 1..1024 links, 1..2^24 chains."""
+    import paper_1311_1056_amd as cl
+    assert cl.cl_lattice_bytes(cl.make_desc((46, 46, 46, 46), 6.0)) > 9 * 10**9
+    assert cl.cl_lattice_bytes(cl.make_desc((56, 56, 56, 56), 6.0, precision=cl.CL_MIXED)) > 9 * 10**9
+    for dims, prec in (((48, 48, 48, 48), cl.CL_FP64), ((58, 58, 58, 58), cl.CL_MIXED),
+                       ((46, 46, 46, 52), cl.CL_FP64)):
+        with pytest.raises(cl.ClError) as e:
+            cl.cl_lattice_bytes(cl.make_desc(dims, 6.0, precision=prec))
+        assert e.value.status == cl.CL_EINVAL
+    lib = cl.lib
+    for n, nc, ok in ((1024, 1, True), (1025, 1, False), (0, 1, False), (16, 1 << 24, True), (16, (1 << 24) + 1, False),
+                      (16, 0, False)):
+        d = cl.cl_chain_desc()
+        d.n_links, d.n_chains, d.beta_re, d.beta_im = n, nc, 2.0, 1.0
+        nbytes = ctypes.c_size_t(0)
+        st = lib.cl_chain_bytes(ctypes.byref(d), ctypes.byref(nbytes))
+        assert (st == 0) == ok, (n, nc, st)
+

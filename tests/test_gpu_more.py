@@ -122,15 +122,17 @@ def test_production_size_16x4_full_step(cl, orc):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("dims", [(24, 24, 24, 24), (32, 32, 32, 32)])
-def test_large_lattice_sampled_drift(cl, orc, dims):
-    """24^4 and 32^4 (mixed, and FP64 at 24^4): the drift of sampled links against
-    the oracle, which evaluates each sampled link on its own."""
+@pytest.mark.parametrize("dims,precs", [((24, 24, 24, 24), (1, 0)), ((32, 32, 32, 32), (1,)),
+                                        ((46, 46, 46, 46), (0,)), ((56, 56, 56, 56), (1,))])
+def test_large_lattice_sampled_drift(cl, orc, dims, precs):
+    """24^4, 32^4 and the largest lattices the buffer resources address (46^4
+    FP64, 56^4 mixed): the drift of sampled links (the first and the last
+    among them) against the oracle, which evaluates each sampled link on its
+    own."""
     rng = np.random.default_rng(8)
     V = lu.volume(dims)
     sel = np.sort(rng.choice(4 * V, size=48, replace=False))
     sel = np.concatenate([sel, [0, 4 * V - 1]])
-    precs = [cl.CL_MIXED] + ([cl.CL_FP64] if dims[0] == 24 else [])
     for prec in precs:
         lat = cl.Lattice(dims, 6.0, 1.0, prec, seed=4)
         lat.init(True, 0.3, 0.05)
@@ -141,6 +143,13 @@ def test_large_lattice_sampled_drift(cl, orc, dims):
         err = relerr(K, ref)
         say(f"{dims} prec={prec}: sampled drift rel err {err:.2e}")
         assert err < tol
+        if dims[0] >= 46:
+            # a full step with cooling at the largest size (the prefetching
+            # cooling kernels at their largest chunk count): finite, advanced,
+            # and the cooling lowers the distance
+            lat.run_steps(1, 1e-2, True, 2, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+            o = lat.measure()
+            assert o["step"] == 1 and np.isfinite(o["d"]) and 0 < o["d"] <= o["d_pre"], o
         lat.close()
 
 

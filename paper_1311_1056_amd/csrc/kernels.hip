@@ -289,6 +289,23 @@ __global__ void __launch_bounds__(kBlock) k_pack(const KArgs ka,
     CLGC_END_BLOCKS
 }
 
+// Order of the regions (256 consecutive half-indices) inside one XCD's share
+// of a kernel that deals whole regions to XCDs: x3 fastest.  In half-index
+// order a region's x3 neighbours come a whole x3 slice of regions later, long
+// after its data left the XCD's L2; with the share transposed they run next
+// to it.  A bijection on the share; the identity when the share is not a
+// whole number of x3 slices.
+__device__ __forceinline__ int xcd_region_order(const RunArgs& ra, int region, int nreg)
+{
+    const int per = nreg / kXcds;
+    const int slice_h = ra.Vh / ra.L[3];
+    if (nreg % kXcds || slice_h % kBlock) return region;
+    const int slice = slice_h / kBlock;
+    if (slice == 0 || per % slice || per / slice < 2) return region;
+    const int c3 = per / slice, k = region % per;
+    return region - k + (k % c3) * slice + k / c3;
+}
+
 // ---------------------------------------------------------------------------
 // clover field: F_{mu nu}(x) = sum over the four counter-clockwise leaves L at
 // x in the (mu, nu) plane of (L - L^{-1})
@@ -300,7 +317,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_clover(const KArgs ka,
     CLGC_FOR_BLOCKS(KIND_PLANE)
     // logical block -> (region of 256 half-indices, plane, parity), regions major
     const int P = (lb % 12) >> 1, p = lb & 1;
-    const int h = (lb / 12) * kBlock + (int)threadIdx.x;
+    const int h = xcd_region_order(ra, lb / 12, ra.nblk[KIND_PLANE] / 12) * kBlock + (int)threadIdx.x;
     // in a batched step only the runs with a theta term need the field
     if (h < ra.Vh && !(only_theta && !ra.has_theta)) {
         const int tid_f = P * ra.V + p * ra.Vh + h;
@@ -405,9 +422,9 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
     CLGC_FOR_BLOCKS(KIND_DRIFT)
     // logical block -> (region of 256 half-indices, direction, parity): the eight
     // (mu, parity) blocks of a region are adjacent, so one XCD covers all the
-    // links of a contiguous slab of sites
+    // links of a contiguous slab of sites (its regions in xcd_region_order)
     const int mu = (lb & 7) >> 1, p = lb & 1;
-    const int h = (lb >> 3) * kBlock + (int)threadIdx.x;
+    const int h = xcd_region_order(ra, lb >> 3, ra.nblk[KIND_DRIFT] >> 3) * kBlock + (int)threadIdx.x;
     const int l = (mu * 2 + p) * ra.Vh + h;
     double kn2 = 0.0;
     if (h < ra.Vh) {

@@ -758,6 +758,47 @@ __device__ __forceinline__ void herm_exp_pair(herm3<T> A, herm3<T>& E, herm3<T>&
         Ei = h_square(Ei);
     }
 }
+// exp(A) alone, with the same operations herm_exp_pair applies to A: for -A
+// it reproduces that function's exp(-A) bit for bit (A^2 and the scaling do
+// not see the sign, det flips it, and c1 (-a) equals (-c1) a)
+template <typename T>
+__device__ __forceinline__ void herm_exp_one(herm3<T> A, herm3<T>& E)
+{
+    const T fro2 = A.d0 * A.d0 + A.d1 * A.d1 + A.d2 * A.d2 +
+                   T(2) * (norm2(A.u01) + norm2(A.u02) + norm2(A.u12));
+    int k = 0;
+    if (fro2 > T(1)) {
+        // a non-finite norm (a runaway) takes no squarings; its infinite log
+        // converted to int would give a loop of 2^31 squarings
+        const T lk = T(0.5) * log2(fro2);
+        k = lk < T(1100) ? (int)ceil(lk) : 0;
+        const T sc = ldexp(T(1), -k);
+        A.d0 *= sc;
+        A.d1 *= sc;
+        A.d2 *= sc;
+        A.u01 = sc * A.u01;
+        A.u02 = sc * A.u02;
+        A.u12 = sc * A.u12;
+    }
+    const herm3<T> A2 = h_square(A);
+    const T s = T(0.5) * (A2.d0 + A2.d1 + A2.d2);
+    // det of a Hermitian matrix (real)
+    const cx<T> w = A.u01 * A.u12 * conj(A.u02);
+    const T t = A.d0 * A.d1 * A.d2 + T(2) * w.re - A.d0 * norm2(A.u12) - A.d1 * norm2(A.u02) -
+                A.d2 * norm2(A.u01);
+    T f0, f1, f2;
+    // The series needs exp_terms terms for |A|_F <= 1; a cooling step's A is
+    // usually far smaller, and for |A|_F <= 1/8 the terms after the first 10
+    // (FP64; 6 in FP32) add at most 3e-18 (1e-10) relative.  The choice is
+    // taken per wavefront, so the loop stays uniform.
+    constexpr int kShort = sizeof(T) == 8 ? 10 : 6;
+    if (__all(fro2 * ldexp(T(1), -2 * k) <= T(1.0 / 64.0)))
+        ch_exp_coeffs_real<T, kShort>(s, t, f0, f1, f2);
+    else
+        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, t, f0, f1, f2);
+    E = h_poly(f0, f1, f2, A, A2);
+    for (int i = 0; i < k; ++i) E = h_square(E);
+}
 
 // H U for Hermitian H
 template <typename T>
@@ -885,6 +926,26 @@ __device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm
     A.u12 = coef * G.u12;
     herm_exp_pair(A, E, Ei);
 }
+// the same for one of the pair: coef < 0 gives Omega, coef > 0 Omega^-1
+template <typename T>
+__device__ __forceinline__ void site_omega_one(herm3<T> G, T coef, herm3<T>& E)
+{
+    G.d0 = quad_sum(G.d0);
+    G.d1 = quad_sum(G.d1);
+    G.d2 = quad_sum(G.d2);
+    G.u01 = {quad_sum(G.u01.re), quad_sum(G.u01.im)};
+    G.u02 = {quad_sum(G.u02.re), quad_sum(G.u02.im)};
+    G.u12 = {quad_sum(G.u12.re), quad_sum(G.u12.im)};
+    const T tr = (G.d0 + G.d1 + G.d2) * T(1.0 / 3.0);
+    herm3<T> A;
+    A.d0 = coef * (G.d0 - tr);
+    A.d1 = coef * (G.d1 - tr);
+    A.d2 = coef * (G.d2 - tr);
+    A.u01 = coef * G.u01;
+    A.u02 = coef * G.u02;
+    A.u12 = coef * G.u12;
+    herm_exp_one(A, E);
+}
 
 // In both kernels the link loads are issued first: the run's state (status,
 // the unitarity norm entering the step, alpha) only sets the coefficient,
@@ -931,9 +992,12 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
                     cr->hist_n = iter + 1;
                 }
             }
-            herm3<T> E, Ei;
-            site_omega(G, T(-4.0 * ra.eps_c * alpha_ad), E, Ei);
-            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
+            // lane 0 of the quad forms Omega, lane 1 Omega^-1 (the others do
+            // not store)
+            const T coef = T(-4.0 * ra.eps_c * alpha_ad);
+            herm3<T> E;
+            site_omega_one(G, mu == 1 ? -coef : coef, E);
+            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
         }
     }
     CLGC_END_BLOCKS
@@ -1056,9 +1120,9 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
                 h_add_uudag(G, Af);
                 h_sub_udagu(G, Ab);
             }
-            herm3<T> E, Ei;
-            site_omega(G, coef, E, Ei);
-            if (ok && lok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, mu == 0 ? E : Ei);
+            herm3<T> E;
+            site_omega_one(G, mu == 1 ? -coef : coef, E);
+            if (ok && lok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
             h = hn;
             lok = lokn;
             Af = Nf;

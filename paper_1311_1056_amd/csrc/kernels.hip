@@ -653,11 +653,31 @@ __global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
 // exponential has real Cayley-Hamilton coefficients; Omega_x^{-1} =
 // exp(+4 eps alpha G_x) uses the same series with det -> -det.
 
+// the value of lane (l ^ 1) or (l ^ 2) of the quad, moved by DPP quad_perm
+// (CTRL 0xB1: lanes 1 0 3 2; 0x4E: lanes 2 3 0 1) in registers rather than
+// through the LDS crossbar
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// the sum over the quad, the same in its four lanes (each adds the same two
+// pairs in the same order)
 template <typename T>
 __device__ __forceinline__ T quad_sum(T v)
 {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
+    v += quad_perm<0xB1>(v);
+    v += quad_perm<0x4E>(v);
     return v;
 }
 
@@ -1240,12 +1260,12 @@ __global__ void __launch_bounds__(kBlock) k_gradnorm(const KArgs ka, int iter)
                     h_sub_udagu(G, ldU<T>(ra, mu, site_move(ra, x, mu, -1)));
                 }
             }
-            G.d0 += __shfl_xor(G.d0, 1, 64);
-            G.d1 += __shfl_xor(G.d1, 1, 64);
-            G.d2 += __shfl_xor(G.d2, 1, 64);
-            G.u01 = {G.u01.re + __shfl_xor(G.u01.re, 1, 64), G.u01.im + __shfl_xor(G.u01.im, 1, 64)};
-            G.u02 = {G.u02.re + __shfl_xor(G.u02.re, 1, 64), G.u02.im + __shfl_xor(G.u02.im, 1, 64)};
-            G.u12 = {G.u12.re + __shfl_xor(G.u12.re, 1, 64), G.u12.im + __shfl_xor(G.u12.im, 1, 64)};
+            G.d0 += quad_perm<0xB1>(G.d0);
+            G.d1 += quad_perm<0xB1>(G.d1);
+            G.d2 += quad_perm<0xB1>(G.d2);
+            G.u01 = {G.u01.re + quad_perm<0xB1>(G.u01.re), G.u01.im + quad_perm<0xB1>(G.u01.im)};
+            G.u02 = {G.u02.re + quad_perm<0xB1>(G.u02.re), G.u02.im + quad_perm<0xB1>(G.u02.im)};
+            G.u12 = {G.u12.re + quad_perm<0xB1>(G.u12.re), G.u12.im + quad_perm<0xB1>(G.u12.im)};
             if (sx < ra.V && half == 0) {
                 const double r3 = 0.57735026918962576451;
                 fs += 4.0 * (fabs((double)G.u01.re) + fabs((double)G.u01.im) + fabs((double)G.u02.re) +

@@ -19,17 +19,48 @@ namespace clgc {
 // ---------------------------------------------------------------------------
 // reductions
 
+// a value moved between lanes by a DPP permutation, in registers rather than
+// through the LDS crossbar: CTRL 0xB1 lanes 1 0 3 2 of each quad (l ^ 1),
+// 0x4E lanes 2 3 0 1 (l ^ 2), 0x141 the mirror within 8 lanes, 0x140 the
+// mirror within 16
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum / max over the wavefront, the same bits in every lane: a butterfly whose
+// steps pair lanes by involutions (xor 32 and 16 by shuffle, then the 16- and
+// 8-lane mirrors and the two quad swaps by DPP), so each lane combines the
+// same pairs in the same order.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += __shfl_xor(v, 32, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += dpp_move<0x140>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0xB1>(v);
     return v;
 }
 
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    v = fmax(v, __shfl_xor(v, 32, 64));
+    v = fmax(v, __shfl_xor(v, 16, 64));
+    v = fmax(v, dpp_move<0x140>(v));
+    v = fmax(v, dpp_move<0x141>(v));
+    v = fmax(v, dpp_move<0x4E>(v));
+    v = fmax(v, dpp_move<0xB1>(v));
     return v;
 }
 
@@ -653,31 +684,13 @@ __global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
 // exponential has real Cayley-Hamilton coefficients; Omega_x^{-1} =
 // exp(+4 eps alpha G_x) uses the same series with det -> -det.
 
-// the value of lane (l ^ 1) or (l ^ 2) of the quad, moved by DPP quad_perm
-// (CTRL 0xB1: lanes 1 0 3 2; 0x4E: lanes 2 3 0 1) in registers rather than
-// through the LDS crossbar
-template <int CTRL>
-__device__ __forceinline__ float quad_perm(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
-
-template <int CTRL>
-__device__ __forceinline__ double quad_perm(double v)
-{
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
 // the sum over the quad, the same in its four lanes (each adds the same two
 // pairs in the same order)
 template <typename T>
 __device__ __forceinline__ T quad_sum(T v)
 {
-    v += quad_perm<0xB1>(v);
-    v += quad_perm<0x4E>(v);
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
     return v;
 }
 
@@ -1260,12 +1273,12 @@ __global__ void __launch_bounds__(kBlock) k_gradnorm(const KArgs ka, int iter)
                     h_sub_udagu(G, ldU<T>(ra, mu, site_move(ra, x, mu, -1)));
                 }
             }
-            G.d0 += quad_perm<0xB1>(G.d0);
-            G.d1 += quad_perm<0xB1>(G.d1);
-            G.d2 += quad_perm<0xB1>(G.d2);
-            G.u01 = {G.u01.re + quad_perm<0xB1>(G.u01.re), G.u01.im + quad_perm<0xB1>(G.u01.im)};
-            G.u02 = {G.u02.re + quad_perm<0xB1>(G.u02.re), G.u02.im + quad_perm<0xB1>(G.u02.im)};
-            G.u12 = {G.u12.re + quad_perm<0xB1>(G.u12.re), G.u12.im + quad_perm<0xB1>(G.u12.im)};
+            G.d0 += dpp_move<0xB1>(G.d0);
+            G.d1 += dpp_move<0xB1>(G.d1);
+            G.d2 += dpp_move<0xB1>(G.d2);
+            G.u01 = {G.u01.re + dpp_move<0xB1>(G.u01.re), G.u01.im + dpp_move<0xB1>(G.u01.im)};
+            G.u02 = {G.u02.re + dpp_move<0xB1>(G.u02.re), G.u02.im + dpp_move<0xB1>(G.u02.im)};
+            G.u12 = {G.u12.re + dpp_move<0xB1>(G.u12.re), G.u12.im + dpp_move<0xB1>(G.u12.im)};
             if (sx < ra.V && half == 0) {
                 const double r3 = 0.57735026918962576451;
                 fs += 4.0 * (fabs((double)G.u01.re) + fabs((double)G.u01.im) + fabs((double)G.u02.re) +

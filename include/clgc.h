@@ -97,10 +97,13 @@ cl_status cl_lattice_create(const cl_lattice_desc* desc, void* dev_buf, size_t b
                             void* hip_stream, cl_lattice** out);
 cl_status cl_lattice_destroy(cl_lattice* lat);
 
-/* perturbed = 0: cold start U = 1.  perturbed = 1: U = exp(i lambda_a (x_a + i y_a))
+/* Start configuration.  The paper does not give one; the perturbed start has
+ * the form of the SL(3,C) elements of the section on gauge cooling (the
+ * exponential of i omega_a lambda_a with complex omega_a).
+ * perturbed = 0: cold start U = 1.  perturbed = 1: U = exp(i lambda_a (x_a + i y_a))
  * with x_a ~ N(0, sigma_x^2), y_a ~ N(0, sigma_y^2) from Philox stream tag 1
  * (draws 0..3 give x_1..x_8, draws 4..7 give y_1..y_8).  Resets the step counter
- * and the adaptive bound.  Asynchronous. */
+ * and the adaptive bound and clears the per-step record.  Asynchronous. */
 cl_status cl_lattice_init(cl_lattice* lat, int perturbed, double sigma_x, double sigma_y);
 
 /* Copy all links from / to a host array of V*4*18 doubles (layout above).
@@ -108,7 +111,8 @@ cl_status cl_lattice_init(cl_lattice* lat, int perturbed, double sigma_x, double
 cl_status cl_lattice_set_links(cl_lattice* lat, const double* host, size_t n_doubles);
 cl_status cl_lattice_get_links(cl_lattice* lat, double* host, size_t n_doubles);
 
-/* Step counter n and adaptive bound B (for checkpoint / resume).  Synchronous. */
+/* Step counter n and adaptive bound B (for checkpoint / resume).  set_state
+ * clears the per-step record.  Synchronous. */
 cl_status cl_lattice_get_state(cl_lattice* lat, int64_t* step, double* bound);
 cl_status cl_lattice_set_state(cl_lattice* lat, int64_t step, double bound);
 
@@ -130,12 +134,21 @@ cl_status cl_langevin_step(cl_lattice* lat, const cl_step_desc* step, double* ep
  * unorm_after: if non-NULL, waits and returns d of the cooled links. */
 cl_status cl_gauge_cool(cl_lattice* lat, const cl_cool_desc* cool, double* unorm_after);
 
-/* d = (1/12V) sum_{x,mu} Tr(U U^dagger - 1) of the current links (the
- * distance from SU(3) averaged over links).  Synchronous. */
+/* d = (1/12V) sum_{x,mu} Tr(U U^dagger - 1) of the current links: the
+ * one-link distance from the unitary manifold, eq. (d) of the section on the
+ * one-link model, averaged over links; (1/N) Tr U U^dagger >= 1 (section on
+ * gauge cooling) makes it >= 0, with 0 exactly on SU(3).  Synchronous.
+ * CL_ENONFINITE if the lattice's state went non-finite. */
 cl_status cl_unitarity_norm(cl_lattice* lat, double* d);
 
-/* Plaquette, topological charge (clover form of the signed-index density),
- * action, distance and the control state.  Synchronous. */
+/* Observables of the current links (section on SU(3) with a theta term):
+ * the plaquette, the topological charge Q_L = sum_x q_L(x) with the density of
+ * eq. (eq:st) in its equivalent clover form, the action S = S_W - i theta Q_L
+ * of the same section (S_W the Wilson action), the distance d of eq. (d), and
+ * the control state (step size, Kmax, alpha_ad, bound, step counter).
+ * Accumulated in FP64 in both precisions; a mixed-precision lattice forms the
+ * clover matrices in FP64 from its FP32 links.  Synchronous.  CL_ENONFINITE if
+ * the state went non-finite (out is still filled). */
 cl_status cl_measure(cl_lattice* lat, cl_obs* out);
 
 /* Drift Khat of every link for the current configuration, copied to a host
@@ -149,9 +162,36 @@ cl_status cl_compute_drift(cl_lattice* lat, double* host_K, size_t n_doubles);
 cl_status cl_cool_history(cl_lattice* lat, double* unorm, double* alpha, int cap, int* n);
 
 /* n_steps x (one CL update + cooling), all enqueued without host
- * synchronisation (what a production loop runs).  Asynchronous. */
+ * synchronisation (what a production loop runs): the alternation of Langevin
+ * updates and cooling steps of the section on the SU(2) Polyakov chain model,
+ * applied to the SU(3) lattice.  Replayed from captured graphs (blocks of
+ * eight steps, then single steps), captured on first use for these
+ * parameters.  With the record on (cl_record_enable) every step's
+ * observables are written to the device record as well.  Asynchronous. */
 cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_desc* cool,
                        int n_steps);
+
+/* Capture and instantiate the graphs cl_run_steps replays for these
+ * parameters (and the current record setting) without running them, so that
+ * no later call pays for a capture.  Sets the step and cooling parameters as
+ * cl_run_steps would.  Synchronous on the host (no device work). */
+cl_status cl_run_prepare(cl_lattice* lat, const cl_step_desc* step, const cl_cool_desc* cool);
+
+/* Per-step record of cl_run_steps (the paper's results are Langevin-time
+ * series: the running <Q_L> and the distance along the Langevin time).  While
+ * enabled, each CL step's observables, measured on the links it leaves after
+ * its cooling, go to a ring of the last 4096 steps in the lattice's device
+ * buffer, with no host synchronisation: the measurement runs at the start of
+ * the next step (with a theta term in FP64 it reuses the clover field that
+ * step builds for its drift) and after each call's last step.  Disabled by
+ * default.  Each entry is 12 doubles:
+ *   step, d_pre, d, Re P, Im P, Re Q, Im Q, Re S, Im S, eps, Kmax, alpha_ad
+ * (as in cl_obs; d_pre before and d after the step's cooling). */
+cl_status cl_record_enable(cl_lattice* lat, int enable);
+/* Copy the entries of CL steps first_step .. first_step + n - 1 (1-based,
+ * counted by the step counter) to host[n * 12].  CL_EINVAL if a step is not
+ * in the record (not taken yet, or more than 4096 steps ago).  Synchronous. */
+cl_status cl_record_read(cl_lattice* lat, int64_t first_step, int n, double* host);
 
 /* Kernel kinds reported by cl_timing_read. */
 typedef enum {
@@ -193,6 +233,8 @@ typedef struct {
     int32_t n_steps;           /* CL steps to run (>= 1) */
     double sigma_x, sigma_y;   /* perturbed start as in cl_lattice_init */
     uint64_t tag;              /* caller's label, returned with the result */
+    int32_t keep_links;        /* != 0: keep the final links for cl_server_take_links */
+    int32_t pad;
 } cl_run_desc;
 
 typedef struct {
@@ -226,9 +268,13 @@ cl_status cl_server_step(cl_server* srv, int* n_active, int* n_pending);
 /* Move up to cap finished results into out (oldest first). */
 cl_status cl_server_poll(cl_server* srv, cl_run_result* out, int cap, int* n_done);
 cl_status cl_server_stats_get(cl_server* srv, cl_server_stats* out);
+/* The final links of a finished run submitted with keep_links (host link
+ * layout, V*4*18 doubles), copied once and then released.  CL_EINVAL if the
+ * run is not finished, kept no links or was already taken, or n_doubles does
+ * not match. */
+cl_status cl_server_take_links(cl_server* srv, uint64_t run_id, double* host, size_t n_doubles);
 cl_status cl_server_destroy(cl_server* srv);
 
-/* Message for the last failing call on this thread ("" if none). */
 /* ------------------------------------------------------------------------
  * SU(2) Polyakov chain (section "Adaptive gauge cooling in the SU(2) Polyakov
  * chain model"): n_chains independent chains of n_links SL(2,C) links with
@@ -315,6 +361,7 @@ cl_status cl_chain_measure(cl_chain* ch, cl_chain_obs* out, int cap);
 /* the per-step record of the last recording cl_chain_run: n_steps x n_chains x 6. */
 cl_status cl_chain_record(cl_chain* ch, double* host, size_t n_doubles);
 
+/* Message for the last failing call on this thread ("" if none). */
 const char* cl_last_error(void);
 
 #ifdef __cplusplus

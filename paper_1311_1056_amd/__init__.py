@@ -22,6 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libclgc.so")
 CL_OK, CL_EINVAL, CL_ENOMEM, CL_EHIP, CL_ENONFINITE, CL_EBUDGET = 0, -1, -2, -3, -4, -5
 CL_FP64, CL_MIXED = 0, 1
 CL_ALPHA_FIXED, CL_ALPHA_UNORM, CL_ALPHA_GRAD = 0, 1, 2
+# fields of one per-step record entry (cl_record_read)
+RECORD_FIELDS = ("step", "d_pre", "d", "plaq_re", "plaq_im", "q_re", "q_im", "action_re", "action_im", "eps",
+                 "kmax", "alpha")
 KERNEL_KINDS = ("init", "unorm", "pack", "clover", "drift", "update", "cool_omega", "cool_apply", "gradnorm",
                 "measure", "finalize")
 
@@ -50,7 +53,7 @@ class cl_obs(ctypes.Structure):
 class cl_run_desc(ctypes.Structure):
     _fields_ = [("lattice", cl_lattice_desc), ("step", cl_step_desc), ("cool", cl_cool_desc),
                 ("n_steps", ctypes.c_int32), ("sigma_x", ctypes.c_double), ("sigma_y", ctypes.c_double),
-                ("tag", ctypes.c_uint64)]
+                ("tag", ctypes.c_uint64), ("keep_links", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class cl_run_result(ctypes.Structure):
@@ -109,6 +112,10 @@ def _load():
         "cl_compute_drift": [vp, dp, sz],
         "cl_cool_history": [vp, dp, dp, ctypes.c_int, P(ctypes.c_int)],
         "cl_run_steps": [vp, P(cl_step_desc), P(cl_cool_desc), ctypes.c_int],
+        "cl_run_prepare": [vp, P(cl_step_desc), P(cl_cool_desc)],
+        "cl_record_enable": [vp, ctypes.c_int],
+        "cl_record_read": [vp, ctypes.c_int64, ctypes.c_int, dp],
+        "cl_server_take_links": [vp, ctypes.c_uint64, dp, sz],
         "cl_timing_enable": [vp, ctypes.c_int],
         "cl_server_create": [vp, sz, vp, P(vp)],
         "cl_server_submit": [vp, P(cl_run_desc), P(ctypes.c_uint64)],
@@ -251,6 +258,21 @@ class Lattice:
         cd = cl_cool_desc(int(n_cool), float(eps_c), float(alpha), int(mode))
         _check(lib.cl_run_steps(self.handle, ctypes.byref(sd), ctypes.byref(cd), int(n)))
 
+    def run_prepare(self, eps0, adaptive, n_cool, eps_c, alpha=1.0, mode=CL_ALPHA_FIXED, drift_bound=0.0):
+        """Capture the graphs run_steps replays for these parameters now."""
+        sd = cl_step_desc(float(eps0), int(adaptive), float(drift_bound))
+        cd = cl_cool_desc(int(n_cool), float(eps_c), float(alpha), int(mode))
+        _check(lib.cl_run_prepare(self.handle, ctypes.byref(sd), ctypes.byref(cd)))
+
+    def record_enable(self, on=True):
+        _check(lib.cl_record_enable(self.handle, int(on)))
+
+    def record_read(self, first_step, n):
+        """(n, 12) array of per-step record entries, columns RECORD_FIELDS."""
+        a = np.zeros(int(n) * len(RECORD_FIELDS))
+        _check(lib.cl_record_read(self.handle, int(first_step), int(n), _dp(a)))
+        return a.reshape(int(n), len(RECORD_FIELDS))
+
     def unitarity_norm(self):
         d = ctypes.c_double()
         _check(lib.cl_unitarity_norm(self.handle, ctypes.byref(d)))
@@ -310,11 +332,11 @@ class Server:
 
     def submit(self, dims, beta, theta=0.0, precision=CL_FP64, seed=0, n_steps=1, eps0=1e-2, adaptive=True,
                n_cool=10, eps_c=None, alpha=1.0, mode=CL_ALPHA_UNORM, sigma_x=0.3, sigma_y=0.05, tag=0,
-               drift_bound=0.0):
+               drift_bound=0.0, keep_links=False):
         d = cl_run_desc(make_desc(dims, beta, theta, precision, seed),
                         cl_step_desc(float(eps0), int(adaptive), float(drift_bound)),
                         cl_cool_desc(int(n_cool), float(eps0 if eps_c is None else eps_c), float(alpha), int(mode)),
-                        int(n_steps), float(sigma_x), float(sigma_y), int(tag))
+                        int(n_steps), float(sigma_x), float(sigma_y), int(tag), int(bool(keep_links)), 0)
         rid = ctypes.c_uint64()
         _check(lib.cl_server_submit(self.handle, ctypes.byref(d), ctypes.byref(rid)))
         return rid.value
@@ -335,6 +357,12 @@ class Server:
                         "t_finish": r.t_finish, "step_ms_p50": r.step_ms_p50, "step_ms_p99": r.step_ms_p99,
                         "link_updates": r.link_updates})
         return out
+
+    def take_links(self, run_id, dims):
+        """Final links (V, 4, 18) of a finished run submitted with keep_links."""
+        a = np.zeros(int(np.prod(dims)) * 72)
+        _check(lib.cl_server_take_links(self.handle, int(run_id), _dp(a), a.size))
+        return a.reshape(-1, 4, 18)
 
     def stats(self):
         st = cl_server_stats()

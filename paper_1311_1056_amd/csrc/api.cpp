@@ -1,7 +1,7 @@
 // api.cpp -- the C ABI of include/clgc.h on top of the kernels.
 //
 // A lattice lives entirely inside the caller's device buffer:
-//   [links U][drift K][clover F][partials][cooling partials][Ctrl][RunArgs][BatchHdr]
+//   [links U][drift K][clover F][partials][cooling partials][Ctrl][RunArgs][BatchHdr][record]
 // (K and F are adjacent so that together they can stage the host link
 // array in set/get_links).  Parameters reach the device through a one-thread
 // kernel that copies a RunArgs struct passed by value, so every call stays
@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -65,6 +66,8 @@ Layout layout_of(const cl_lattice_desc& d)
     off = align256(off + sizeof(RunArgs));
     L.hdr = off;
     off = align256(off + sizeof(BatchHdr));
+    L.rec = off;
+    off = align256(off + sizeof(double) * kRecCap * kRecFields);
     L.total = off;
     return L;
 }
@@ -207,10 +210,34 @@ void soa_to_host(const cl_lattice* lat, const void* raw, double* host)
                 }
 }
 
+// Measure the current links into the per-step record (the entry of the CL
+// step that produced them).  FP64 with a theta term takes the clover field,
+// built here unless it is current; otherwise each site forms its clover
+// matrices itself in FP64.
+cl_status enqueue_record(cl_lattice* lat)
+{
+    const bool from_f = lat->prec == CL_FP64 && lat->has_theta;
+    if (from_f && !lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
+    if (from_f) lat->F_valid = true;
+    TIMED(lat, CL_K_MEASURE, launch_measure(lat->L, lat->prec, from_f));
+    TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_RECORD, 0));
+    return CL_OK;
+}
+
 cl_status enqueue_step(cl_lattice* lat)
 {
     const bool theta = lat->has_theta;
-    if (theta && !lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
+    if (theta && !lat->F_valid) {
+        TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
+        lat->F_valid = true;
+    }
+    // recording: the links entering this step are the ones the previous step
+    // left after its cooling, and with a theta term their clover field was
+    // just built for the drift
+    if (lat->record) {
+        cl_status st = enqueue_record(lat);
+        if (st) return st;
+    }
     TIMED(lat, CL_K_DRIFT, launch_drift(lat->L, lat->prec, theta));
     TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_DRIFT, 0));
     TIMED(lat, CL_K_UPDATE, launch_update(lat->L, lat->prec));
@@ -247,6 +274,7 @@ cl_status ensure_graph(cl_lattice* lat, int n_cool, int n_rep, hipGraphExec_t& s
     key.n_cool = n_cool;
     key.mode = lat->args.mode;
     key.theta = lat->has_theta ? 1 : 0;
+    key.record = lat->record ? 1 : 0;
     key.args = lat->args;
     if (slot && std::memcmp(&key, &slot_key, sizeof key) == 0) return CL_OK;
     if (slot) {
@@ -282,6 +310,8 @@ cl_status ensure_graph(cl_lattice* lat, int n_cool, int n_rep, hipGraphExec_t& s
     if (e != hipSuccess) return fail(CL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     slot = ex;
     std::memcpy(&slot_key, &key, sizeof key);
+    // move the graph's launch data to the device now rather than at its first launch
+    HIP_TRY(hipGraphUpload(ex, lat->stream));
     return CL_OK;
 }
 
@@ -341,6 +371,7 @@ cl_status cl_lattice_create(const cl_lattice_desc* desc, void* dev_buf, size_t b
     a.th_re = desc->theta_re;
     a.th_im = desc->theta_im;
     a.seed = desc->seed;
+    a.rec = (double*)(lat->base + lay.rec);
     a.eps0 = 1e-2;
     a.eps_c = 1e-2;
     a.alpha = 1.0;
@@ -404,6 +435,8 @@ cl_status cl_lattice_init(cl_lattice* lat, int perturbed, double sigma_x, double
         return fail(CL_EINVAL, "sigma must be finite");
     HIP_TRY(launch_init(lat->L, lat->prec, perturbed ? 1 : 0, sigma_x, sigma_y));
     HIP_TRY(launch_finalize(lat->L, FIN_INIT, 0));
+    // the step counter restarts: no entry of an earlier trajectory may remain
+    HIP_TRY(launch_zero(lat->args.rec, kRecCap * kRecFields, lat->stream));
     lat->F_valid = false;
     return CL_OK;
 }
@@ -452,6 +485,7 @@ cl_status cl_lattice_set_state(cl_lattice* lat, int64_t step, double bound)
     if (!lat) return fail(CL_EINVAL, "lattice is NULL");
     if (step < 0 || step > 0xFFFFFFFFll) return fail(CL_EINVAL, "step out of range");
     HIP_TRY(launch_write_state(lat->d_ctrl, step, bound, lat->stream));
+    HIP_TRY(launch_zero(lat->args.rec, kRecCap * kRecFields, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     return CL_OK;
 }
@@ -500,7 +534,7 @@ cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_
             if ((st = enqueue_step(lat)) != CL_OK) return st;
             if ((st = enqueue_cool(lat, cool->n_steps)) != CL_OK) return st;
         }
-        return CL_OK;
+        return lat->record ? enqueue_record(lat) : CL_OK;
     }
     // whole blocks of kGraphSteps steps from one graph (the gap between two graph
     // launches is paid once per block), the remainder from the one-step graph
@@ -514,6 +548,53 @@ cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_
         for (int i = 0; i < rest; ++i) HIP_TRY(hipGraphLaunch(lat->step_graph, lat->stream));
     }
     lat->F_valid = false;
+    // the last step's entry (the graph steps recorded the ones before it)
+    return lat->record ? enqueue_record(lat) : CL_OK;
+}
+
+cl_status cl_run_prepare(cl_lattice* lat, const cl_step_desc* step, const cl_cool_desc* cool)
+{
+    if (!lat) return fail(CL_EINVAL, "lattice is NULL");
+    cl_status st = set_step_params(lat, step);
+    if (st) return st;
+    if ((st = set_cool_params(lat, cool)) != CL_OK) return st;
+    if ((st = ensure_graph(lat, cool->n_steps, kGraphSteps, lat->multi_graph, lat->multi_key)) != CL_OK) return st;
+    return ensure_graph(lat, cool->n_steps, 1, lat->step_graph, lat->graph_key);
+}
+
+cl_status cl_record_enable(cl_lattice* lat, int enable)
+{
+    if (!lat) return fail(CL_EINVAL, "lattice is NULL");
+    lat->record = enable != 0;
+    return CL_OK;
+}
+
+cl_status cl_record_read(cl_lattice* lat, int64_t first_step, int n, double* host)
+{
+    if (!lat || (n > 0 && !host)) return fail(CL_EINVAL, "NULL argument");
+    if (n < 0 || first_step < 1) return fail(CL_EINVAL, "first_step must be >= 1 and n >= 0");
+    Ctrl c;
+    cl_status st = read_ctrl(lat, &c);
+    if (st) return st;
+    const int64_t last = first_step + n - 1;
+    if (n > 0 && (last > c.step || first_step <= c.step - kRecCap))
+        return fail(CL_EINVAL, "steps %lld..%lld not in the record (it holds the last %d of %lld steps)",
+                    (long long)first_step, (long long)last, kRecCap, (long long)c.step);
+    const double* rec = lat->args.rec;
+    int done = 0;
+    while (done < n) {
+        const int64_t i = (first_step - 1 + done) % kRecCap;
+        const int k = (int)std::min<int64_t>(n - done, kRecCap - i);
+        HIP_TRY(hipMemcpyAsync(host + (size_t)done * kRecFields, rec + (size_t)i * kRecFields,
+                               sizeof(double) * kRecFields * k, hipMemcpyDeviceToHost, lat->stream));
+        done += k;
+    }
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    // an entry holds its own step number; a step run while the record was off
+    // left its slot without one
+    for (int k = 0; k < n; ++k)
+        if (host[(size_t)k * kRecFields] != (double)(first_step + k))
+            return fail(CL_EINVAL, "step %lld was not recorded", (long long)(first_step + k));
     return CL_OK;
 }
 
@@ -531,9 +612,11 @@ cl_status cl_unitarity_norm(cl_lattice* lat, double* d)
 cl_status cl_measure(cl_lattice* lat, cl_obs* out)
 {
     if (!lat || !out) return fail(CL_EINVAL, "NULL argument");
-    if (!lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
-    lat->F_valid = true;
-    TIMED(lat, CL_K_MEASURE, launch_measure(lat->L, lat->prec));
+    // FP64 reads the clover field; mixed precision forms it in FP64 per site
+    const bool from_f = lat->prec == CL_FP64;
+    if (from_f && !lat->F_valid) TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
+    if (from_f) lat->F_valid = true;
+    TIMED(lat, CL_K_MEASURE, launch_measure(lat->L, lat->prec, from_f));
     TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_MEASURE, 0));
     Ctrl c;
     cl_status st = read_ctrl(lat, &c);
@@ -553,7 +636,8 @@ cl_status cl_measure(cl_lattice* lat, cl_obs* out)
     // -i theta Q = -i (tr + i ti)(qr + i qi) = (ti qr + tr qi) - i (tr qr - ti qi)
     out->action[0] = sw_re + (ti * out->q[0] + tr * out->q[1]);
     out->action[1] = sw_im - (tr * out->q[0] - ti * out->q[1]);
-    out->unorm_d = c.unorm / (12.0 * V) - 1.0;
+    // d of the links measured here (their norms summed in FP64)
+    out->unorm_d = c.obs[6] / (12.0 * V) - 1.0;
     out->d_pre = c.d_pre;
     out->eps = c.eps;
     out->kmax = c.kmax;

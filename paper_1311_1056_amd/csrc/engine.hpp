@@ -40,11 +40,14 @@ hipError_t launch_update(const Launch& L, int prec);
 // phase 0: even-site Omega (k_cool_omega); phase 1: apply both half-sweeps (k_cool_apply)
 hipError_t launch_cool(const Launch& L, int prec, int phase, int iter);
 hipError_t launch_gradnorm(const Launch& L, int prec, int iter);
-hipError_t launch_measure(const Launch& L, int prec);
+// from_f (FP64 only): the clover field of the current links is in F; otherwise
+// each site forms its clover matrices itself in FP64 (always for mixed precision)
+hipError_t launch_measure(const Launch& L, int prec, bool from_f);
 hipError_t launch_finalize(const Launch& L, int what, int iter);
 hipError_t launch_gather(const Launch& L, GatherRec* out);
 hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st);
 hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st);
+hipError_t launch_zero(double* p, int n, hipStream_t st);
 
 // Cooling kernels use at most kMaxCoolBlocks logical blocks per run (512
 // blocks of 256 threads at two waves per SIMD already fill the 256 CUs); a

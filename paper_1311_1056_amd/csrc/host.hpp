@@ -26,7 +26,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // byte offsets of a lattice's pieces inside its device buffer
 struct Layout {
-    size_t U, K, F, part, cpart, ctrl, args, hdr, total;
+    size_t U, K, F, part, cpart, ctrl, args, hdr, rec, total;
 };
 
 Layout layout_of(const cl_lattice_desc& d);
@@ -37,7 +37,7 @@ cl_status check_desc(const cl_lattice_desc* d);
 // what a captured step graph depends on: the launch sequence and the RunArgs
 // copy its kernel arguments carry (compared bytewise; zero-filled first)
 struct GraphKey {
-    int n_cool, mode, theta, pad;
+    int n_cool, mode, theta, record;
     clgc::RunArgs args;
 };
 
@@ -60,6 +60,7 @@ struct cl_lattice {
     clgc::Launch L;
     bool F_valid;      // clover field matches the current links
     bool has_theta;
+    bool record;       // cl_run_steps measures every step into the device record
     // benchmark instrumentation (cl_timing_enable)
     bool timing;
     struct Mark {

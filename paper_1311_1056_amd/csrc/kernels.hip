@@ -876,11 +876,12 @@ __device__ __forceinline__ mat3<T> mul_h(const mat3<T>& U, const herm3<T>& H)
 // link is read and written once per cooling step, and each product is the one
 // the separate half-sweeps would evaluate, in the same order.
 
-// the 18 reals of (Omega, Omega^-1) of even site h: value j at OM[j * Vh + h]
-template <typename T>
+// the 18 reals of (Omega, Omega^-1) of even site h: value j at OM[j * Vh + h],
+// FP64 in both precisions (the drift buffer holds 72 V reals of the link
+// type, at least the 9 V doubles this needs)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t omega_rsrc(const RunArgs& ra)
 {
-    const uint32_t bytes = 18u * (uint32_t)ra.Vh * (uint32_t)sizeof(T);
+    const uint32_t bytes = 18u * (uint32_t)ra.Vh * (uint32_t)sizeof(double);
     return __builtin_amdgcn_make_buffer_rsrc(ra.K, (short)0, (int)bytes, kBufferWord3);
 }
 
@@ -995,12 +996,12 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
             const int t = c * kBlock + (int)threadIdx.x;
             const int h = t >> 2, mu = t & 3;
             const bool lane_ok = h < ra.Vh;
-            herm3<T> G = h_zero<T>();
+            herm3<double> G = h_zero<double>();
             if (lane_ok) {
                 const Site x = site_coords(ra, 0, h);
                 const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-                h_add_uudag(G, load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V));
-                h_sub_udagu(G, load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V));
+                h_add_uudag(G, m_to_double(load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V)));
+                h_sub_udagu(G, m_to_double(load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V)));
             }
             // Each wavefront reads the status for itself (there is no barrier
             // here).  Within this launch the word changes only below, in block
@@ -1027,10 +1028,10 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
             }
             // lane 0 of the quad forms Omega, lane 1 Omega^-1 (the others do
             // not store)
-            const T coef = T(-4.0 * ra.eps_c * alpha_ad);
-            herm3<T> E;
+            const double coef = -4.0 * ra.eps_c * alpha_ad;
+            herm3<double> E;
             site_omega_one(G, mu == 1 ? -coef : coef, E);
-            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
         }
     }
     CLGC_END_BLOCKS
@@ -1053,8 +1054,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
             const int t = c * kBlock + (int)threadIdx.x;
             const int h = t >> 2, mu = t & 3;
             const bool lane_ok = h < ra.Vh;
-            herm3<T> G = h_zero<T>();
-            mat3<T> Uf, Ub;
+            herm3<double> G = h_zero<double>();
+            mat3<double> Uf, Ub;
             int of = 0, ob = 0;
             if (lane_ok) {
                 const Site y = site_coords(ra, 1, h);
@@ -1062,22 +1063,22 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
                 of = (mu * 2 + 1) * ra.Vh + h;
                 ob = link_off(ra, mu, yb);
                 const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-                const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
-                Uf = mul_h(load_mat(Uc, of, 4 * ra.V), load_herm<T>(om, site_half(ra, yf), ra.Vh, 9));
-                Ub = h_mul(load_herm<T>(om, site_half(ra, yb), ra.Vh, 0), load_mat(Uc, ob, 4 * ra.V));
+                const __amdgpu_buffer_rsrc_t om = omega_rsrc(ra);
+                Uf = mul_h(m_to_double(load_mat(Uc, of, 4 * ra.V)), load_herm<double>(om, site_half(ra, yf), ra.Vh, 9));
+                Ub = h_mul(load_herm<double>(om, site_half(ra, yb), ra.Vh, 0), m_to_double(load_mat(Uc, ob, 4 * ra.V)));
                 h_add_uudag(G, Uf);
                 h_sub_udagu(G, Ub);
             }
             ok = cr->status == ST_OK;
-            herm3<T> E, Ei;
-            site_omega(G, T(-4.0 * ra.eps_c * cr->alpha_cur), E, Ei);
+            herm3<double> E, Ei;
+            site_omega(G, -4.0 * ra.eps_c * cr->alpha_cur, E, Ei);
             if (ok && lane_ok) {
-                const mat3<T> Nf = h_mul(E, Uf);
-                const mat3<T> Nb = mul_h(Ub, Ei);
+                const mat3<double> Nf = h_mul(E, Uf);
+                const mat3<double> Nb = mul_h(Ub, Ei);
                 cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
-                store_mat(Uw, of, 4 * ra.V, Nf);
-                store_mat(Uw, ob, 4 * ra.V, Nb);
-                un += (double)m_norm2(Nf) + (double)m_norm2(Nb);
+                store_mat(Uw, of, 4 * ra.V, m_cast_from<T>(Nf));
+                store_mat(Uw, ob, 4 * ra.V, m_cast_from<T>(Nb));
+                un += m_norm2(Nf) + m_norm2(Nb);
             }
         }
         // every link is written exactly once: the sum is the unitarity norm of
@@ -1142,20 +1143,20 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
                 cr->hist_n = iter + 1;
             }
         }
-        const T coef = T(-4.0 * ra.eps_c * alpha_ad);
+        const double coef = -4.0 * ra.eps_c * alpha_ad;
         for (int c = c0; c < c1; ++c) {
             int hn = 0;
             bool lokn = false;
             mat3<T> Nf, Nb;
             if (c + 1 < c1) omega_loads(ra, c + 1, hn, lokn, Nf, Nb);
-            herm3<T> G = h_zero<T>();
+            herm3<double> G = h_zero<double>();
             if (lok) {
-                h_add_uudag(G, Af);
-                h_sub_udagu(G, Ab);
+                h_add_uudag(G, m_to_double(Af));
+                h_sub_udagu(G, m_to_double(Ab));
             }
-            herm3<T> E;
+            herm3<double> E;
             site_omega_one(G, mu == 1 ? -coef : coef, E);
-            if (ok && lok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            if (ok && lok && mu < 2) store_herm(omega_rsrc(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
             h = hn;
             lok = lokn;
             Af = Nf;
@@ -1170,7 +1171,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
 template <typename T>
 struct ApplyIn {
     mat3<T> Uf, Ub;
-    herm3<T> Eif, Eb;
+    herm3<double> Eif, Eb;
     int of, ob;
     bool lok;
 };
@@ -1187,10 +1188,10 @@ __device__ __forceinline__ void apply_loads(const RunArgs& ra, int c, ApplyIn<T>
         in.of = (mu * 2 + 1) * ra.Vh + h;
         in.ob = link_off(ra, mu, yb);
         const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-        const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
+        const __amdgpu_buffer_rsrc_t om = omega_rsrc(ra);
         in.Uf = load_mat(Uc, in.of, 4 * ra.V);
-        in.Eif = load_herm<T>(om, site_half(ra, yf), ra.Vh, 9);
-        in.Eb = load_herm<T>(om, site_half(ra, yb), ra.Vh, 0);
+        in.Eif = load_herm<double>(om, site_half(ra, yf), ra.Vh, 9);
+        in.Eb = load_herm<double>(om, site_half(ra, yb), ra.Vh, 0);
         in.Ub = load_mat(Uc, in.ob, 4 * ra.V);
     }
 }
@@ -1210,29 +1211,29 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int it
         if (c0 < c1) apply_loads(ra, c0, cur);
         // (no kernel writes the status during this launch)
         const bool ok = cr->status == ST_OK;
-        const T coef = T(-4.0 * ra.eps_c * cr->alpha_cur);
+        const double coef = -4.0 * ra.eps_c * cr->alpha_cur;
         double un = 0.0;
         for (int c = c0; c < c1; ++c) {
             ApplyIn<T> nxt;
             nxt.lok = false;
             if (c + 1 < c1) apply_loads(ra, c + 1, nxt);
-            herm3<T> G = h_zero<T>();
-            mat3<T> Uf, Ub;
+            herm3<double> G = h_zero<double>();
+            mat3<double> Uf, Ub;
             if (cur.lok) {
-                Uf = mul_h(cur.Uf, cur.Eif);
-                Ub = h_mul(cur.Eb, cur.Ub);
+                Uf = mul_h(m_to_double(cur.Uf), cur.Eif);
+                Ub = h_mul(cur.Eb, m_to_double(cur.Ub));
                 h_add_uudag(G, Uf);
                 h_sub_udagu(G, Ub);
             }
-            herm3<T> E, Ei;
+            herm3<double> E, Ei;
             site_omega(G, coef, E, Ei);
             if (ok && cur.lok) {
-                const mat3<T> Nf = h_mul(E, Uf);
-                const mat3<T> Nb = mul_h(Ub, Ei);
+                const mat3<double> Nf = h_mul(E, Uf);
+                const mat3<double> Nb = mul_h(Ub, Ei);
                 cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
-                store_mat(Uw, cur.of, 4 * ra.V, Nf);
-                store_mat(Uw, cur.ob, 4 * ra.V, Nb);
-                un += (double)m_norm2(Nf) + (double)m_norm2(Nb);
+                store_mat(Uw, cur.of, 4 * ra.V, m_cast_from<T>(Nf));
+                store_mat(Uw, cur.ob, 4 * ra.V, m_cast_from<T>(Nb));
+                un += m_norm2(Nf) + m_norm2(Nb);
             }
             cur = nxt;
         }
@@ -1298,7 +1299,59 @@ __global__ void __launch_bounds__(kBlock) k_gradnorm(const KArgs ka, int iter)
 // measurement: plaquette traces (and of their inverses, for the Wilson
 // action), topological charge density from the clover field, unitarity norm
 
-template <typename T, bool FAST>
+template <typename T>
+__device__ __forceinline__ mat3<double> ldU64(const RunArgs& ra, int mu, const Site& s)
+{
+    return m_to_double(ldU<T>(ra, mu, s));
+}
+
+// F_{mu nu}(x) = sum over the four counter-clockwise leaves L of (L - L^-1),
+// formed in FP64 from links of type T with the leaf products associated as in
+// k_clover; tp / ti get the traces of the first leaf (the plaquette U_{mu nu}(x)) and of
+// its inverse
+template <typename T>
+__device__ __forceinline__ mat3<double> clover_f64(const RunArgs& ra, const Site& x, int mu, int nu, cx<double>& tp,
+                                                   cx<double>& ti)
+{
+    const Site xpm = site_move(ra, x, mu, +1), xpn = site_move(ra, x, nu, +1);
+    const Site xmm = site_move(ra, x, mu, -1), xmn = site_move(ra, x, nu, -1);
+    const Site xmmpn = site_move(ra, xmm, nu, +1), xmmmn = site_move(ra, xmm, nu, -1);
+    const Site xmnpm = site_move(ra, xmn, mu, +1);
+    mat3<double> S = ldU64<T>(ra, nu, x);
+    // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
+    mat3<double> L = (ldU64<T>(ra, mu, x) * ldU64<T>(ra, nu, xpm)) * m_adj(S * ldU64<T>(ra, mu, xpn));
+    tp = m_tr(L);
+    ti = (L.e[1][1] * L.e[2][2] - L.e[1][2] * L.e[2][1]) + (L.e[0][0] * L.e[2][2] - L.e[0][2] * L.e[2][0]) +
+         (L.e[0][0] * L.e[1][1] - L.e[0][1] * L.e[1][0]);
+    mat3<double> F = L - m_adj(L);
+    __builtin_amdgcn_sched_barrier(0);
+    // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
+    {
+        const mat3<double> Umm = ldU64<T>(ra, mu, xmm);
+        L = S * (m_adj(ldU64<T>(ra, nu, xmm) * ldU64<T>(ra, mu, xmmpn)) * Umm);
+        S = Umm;
+    }
+    F = F + (L - m_adj(L));
+    __builtin_amdgcn_sched_barrier(0);
+    // [U_nu(x-mu-nu) U_mu(x-mu)]^{-1} U_mu(x-mu-nu) U_nu(x-nu)
+    {
+        const mat3<double> Unn = ldU64<T>(ra, nu, xmn);
+        L = m_adj(ldU64<T>(ra, nu, xmmmn) * S) * (ldU64<T>(ra, mu, xmmmn) * Unn);
+        S = Unn;
+    }
+    F = F + (L - m_adj(L));
+    __builtin_amdgcn_sched_barrier(0);
+    // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
+    L = m_adj(S) * ((ldU64<T>(ra, mu, xmn) * ldU64<T>(ra, nu, xmnpm)) * m_adj(ldU64<T>(ra, mu, x)));
+    return F + (L - m_adj(L));
+}
+
+// One lane per site.  FROM_F: the clover field of the current links is in F
+// (FP64, built by k_clover); otherwise every site forms its six clover
+// matrices itself, in FP64 whatever the link precision, so a mixed-precision
+// lattice is measured without FP32 rounding of the near-identity leaves
+// (L - L^-1 cancels most of their digits).
+template <typename T, bool FAST, bool FROM_F>
 __global__ void __launch_bounds__(kBlock) k_measure(const KArgs ka)
 {
     __shared__ double lds[7 * 4];
@@ -1308,37 +1361,67 @@ __global__ void __launch_bounds__(kBlock) k_measure(const KArgs ka)
         const int p = tid >= ra.Vh;
         const int h = tid - p * ra.Vh;
         const Site x = site_coords(ra, p, h);
+        if constexpr (FROM_F) {
 #pragma unroll 1
-        for (int mu = 0; mu < 4; ++mu) {
-            const mat3<T> Um = ldU<T>(ra, mu, x);
-            v[6] += (double)m_norm2(Um);
+            for (int mu = 0; mu < 4; ++mu) {
+                const mat3<T> Um = ldU<T>(ra, mu, x);
+                v[6] += (double)m_norm2(Um);
 #pragma unroll 1
-            for (int nu = mu + 1; nu < 4; ++nu) {
-                const mat3<T> Un = ldU<T>(ra, nu, x);
-                const mat3<T> Pm = (Um * ldU<T>(ra, nu, site_move(ra, x, mu, +1))) *
-                                   m_adj(Un * ldU<T>(ra, mu, site_move(ra, x, nu, +1)));
-                const cx<T> tp = m_tr(Pm);
-                const cx<T> ti = (Pm.e[1][1] * Pm.e[2][2] - Pm.e[1][2] * Pm.e[2][1]) +
-                                 (Pm.e[0][0] * Pm.e[2][2] - Pm.e[0][2] * Pm.e[2][0]) +
-                                 (Pm.e[0][0] * Pm.e[1][1] - Pm.e[0][1] * Pm.e[1][0]);
-                v[0] += (double)tp.re;
-                v[1] += (double)tp.im;
-                v[2] += (double)ti.re;
-                v[3] += (double)ti.im;
+                for (int nu = mu + 1; nu < 4; ++nu) {
+                    const mat3<T> Un = ldU<T>(ra, nu, x);
+                    const mat3<T> Pm = (Um * ldU<T>(ra, nu, site_move(ra, x, mu, +1))) *
+                                       m_adj(Un * ldU<T>(ra, mu, site_move(ra, x, nu, +1)));
+                    const cx<T> tp = m_tr(Pm);
+                    const cx<T> ti = (Pm.e[1][1] * Pm.e[2][2] - Pm.e[1][2] * Pm.e[2][1]) +
+                                     (Pm.e[0][0] * Pm.e[2][2] - Pm.e[0][2] * Pm.e[2][0]) +
+                                     (Pm.e[0][0] * Pm.e[1][1] - Pm.e[0][1] * Pm.e[1][0]);
+                    v[0] += (double)tp.re;
+                    v[1] += (double)tp.im;
+                    v[2] += (double)ti.re;
+                    v[3] += (double)ti.im;
+                }
             }
-        }
-        const cx<T>* __restrict__ Fb = (const cx<T>*)ra.F;
-        const int so = p * ra.Vh + h;
-        cx<double> q = {0.0, 0.0};
+            const cx<T>* __restrict__ Fb = (const cx<T>*)ra.F;
+            const int so = p * ra.Vh + h;
+            cx<double> q = {0.0, 0.0};
 #pragma unroll 1
-        for (int P = 0; P < 3; ++P) {
-            const cx<T> t = m_trmul(load_mat(Fb, P * ra.V + so, 6 * ra.V), load_mat(Fb, (5 - P) * ra.V + so, 6 * ra.V));
-            const double sg = P == 1 ? -1.0 : 1.0;
-            q.re += sg * (double)t.re;
-            q.im += sg * (double)t.im;
+            for (int P = 0; P < 3; ++P) {
+                const cx<T> t = m_trmul(load_mat(Fb, P * ra.V + so, 6 * ra.V), load_mat(Fb, (5 - P) * ra.V + so, 6 * ra.V));
+                const double sg = P == 1 ? -1.0 : 1.0;
+                q.re += sg * (double)t.re;
+                q.im += sg * (double)t.im;
+            }
+            v[4] = q.re;
+            v[5] = q.im;
+        } else {
+#pragma unroll 1
+            for (int mu = 0; mu < 4; ++mu) v[6] += m_norm2(ldU64<T>(ra, mu, x));
+            // planes in the pairs (01, 23), (02, 13), (03, 12) of the charge
+            cx<double> q = {0.0, 0.0};
+#pragma unroll 1
+            for (int P = 0; P < 3; ++P) {
+                const int mu2 = P == 0 ? 2 : 1, nu2 = P == 2 ? 2 : 3;
+                cx<double> tp, ti;
+                const mat3<double> Fa = clover_f64<T>(ra, x, 0, P + 1, tp, ti);
+                v[0] += tp.re;
+                v[1] += tp.im;
+                v[2] += ti.re;
+                v[3] += ti.im;
+                __builtin_amdgcn_sched_barrier(0);
+                const mat3<double> Fd = clover_f64<T>(ra, x, mu2, nu2, tp, ti);
+                v[0] += tp.re;
+                v[1] += tp.im;
+                v[2] += ti.re;
+                v[3] += ti.im;
+                const cx<double> t = m_trmul(Fa, Fd);
+                const double sg = P == 1 ? -1.0 : 1.0;
+                q.re += sg * t.re;
+                q.im += sg * t.im;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            v[4] = q.re;
+            v[5] = q.im;
         }
-        v[4] = q.re;
-        v[5] = q.im;
     }
     block_reduce<7>(v, lds);
     store_partials(ra, KIND_SITE, lb, v);
@@ -1418,10 +1501,36 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, i
             }
             break;
         }
-        case FIN_MEASURE: {
+        case FIN_MEASURE:
+        case FIN_RECORD: {
+            double o[7];
             for (int j = 0; j < 7; ++j) {
-                const double tot = gather_partials(ra, KIND_SITE, j, lds);
-                if (threadIdx.x == 0) c->obs[j] = tot;
+                o[j] = gather_partials(ra, KIND_SITE, j, lds);
+                if (threadIdx.x == 0) c->obs[j] = o[j];
+            }
+            // the record entry of CL step n (1-based), measured on the links that
+            // step left after its cooling (the measurement runs before step n + 1
+            // or after a call's last step: either way the step counter is n)
+            if (what == FIN_RECORD && threadIdx.x == 0 && ok && ra.rec && c->step >= 1) {
+                const double V = ra.V;
+                const double qs = -1.0 / (256.0 * M_PI * M_PI);
+                const double qr = qs * o[4], qi = qs * o[5];
+                // S = S_W - i theta Q,  S_W = beta sum_x sum_{mu<nu} [1 - (Tr P + Tr P^-1) / 6]
+                const double swr = ra.beta * (6.0 * V - (o[0] + o[2]) / 6.0);
+                const double swi = -ra.beta * (o[1] + o[3]) / 6.0;
+                double* e = ra.rec + (size_t)((c->step - 1) % kRecCap) * kRecFields;
+                e[0] = (double)c->step;
+                e[1] = c->d_pre;
+                e[2] = o[6] / (12.0 * V) - 1.0;
+                e[3] = o[0] / (18.0 * V);
+                e[4] = o[1] / (18.0 * V);
+                e[5] = qr;
+                e[6] = qi;
+                e[7] = swr + (ra.th_im * qr + ra.th_re * qi);
+                e[8] = swi - (ra.th_re * qr - ra.th_im * qi);
+                e[9] = c->eps;
+                e[10] = c->kmax;
+                e[11] = c->alpha_cur;
             }
             break;
         }
@@ -1459,6 +1568,12 @@ __global__ void k_gather(const KArgs ka, GatherRec* out)
 __global__ void k_write_args(RunArgs* dst, RunArgs src)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = src;
+}
+
+// zero n doubles (a kernel rather than a memset: safe under graph capture)
+__global__ void k_zero(double* p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
 }
 
 __global__ void k_write_state(Ctrl* c, int64_t step, double bound)
@@ -1604,10 +1719,11 @@ hipError_t launch_gradnorm(const Launch& L, int prec, int iter)
     return hipGetLastError();
 }
 
-hipError_t launch_measure(const Launch& L, int prec)
+hipError_t launch_measure(const Launch& L, int prec, bool from_f)
 {
-    if (prec) CLGC_LAUNCH((k_measure<float, FAST_>), KIND_SITE);
-    else CLGC_LAUNCH((k_measure<double, FAST_>), KIND_SITE);
+    if (prec) CLGC_LAUNCH((k_measure<float, FAST_, false>), KIND_SITE);
+    else if (from_f) CLGC_LAUNCH((k_measure<double, FAST_, true>), KIND_SITE);
+    else CLGC_LAUNCH((k_measure<double, FAST_, false>), KIND_SITE);
     return hipGetLastError();
 }
 
@@ -1632,6 +1748,12 @@ hipError_t launch_gather(const Launch& L, GatherRec* out)
 hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st)
 {
     hipLaunchKernelGGL(k_write_args, dim3(1), dim3(64), 0, st, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

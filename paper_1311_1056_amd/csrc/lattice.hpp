@@ -26,6 +26,9 @@ constexpr int kBlock = 256;        // threads per logical block, all kernels
 constexpr int kXcds = 8;           // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kMaxRuns = 256;      // runs in one batched launch
 constexpr int kMaxCoolHist = 64;   // cooling steps per call kept in the history
+constexpr int kRecCap = 4096;      // CL steps kept in a lattice's per-step record (a ring)
+// one record entry: step, d_pre, d, P re/im, Q re/im, S re/im, eps, Kmax, alpha_ad
+constexpr int kRecFields = 12;
 
 // logical-block kinds: what one thread owns
 enum Kind : int {
@@ -33,13 +36,13 @@ enum Kind : int {
     KIND_SITE = 1,   // one site: measurement                  (V threads)
     KIND_COOL = 2,   // one (site of one parity, mu): cooling  (2V threads)
     KIND_PLANE = 3,  // one (site, plane): clover field        (6V threads)
-    KIND_DRIFT = 4,  // one chain (forward/backward) of a link: drift (8V threads)
+    KIND_DRIFT = 4,  // one (link, 256-site region): drift    (4V threads)
     NKIND = 5
 };
 
 // what a finalize launch reduces
 enum Finalize : int { FIN_INIT = 0, FIN_UNORM = 1, FIN_DRIFT = 2, FIN_UPDATE = 3, FIN_COOL = 4,
-                      FIN_MEASURE = 6 };
+                      FIN_MEASURE = 6, FIN_RECORD = 7 };
 
 enum Status : int { ST_OK = 0, ST_NONFINITE = 1 };
 
@@ -82,6 +85,7 @@ struct RunArgs {
     double eps_c, alpha;
     int n_cool;        // cooling steps of the current call (batched: this run's own count)
     int nblk[NKIND];   // logical blocks of this run per kind
+    double* rec;       // per-step record, kRecCap entries of kRecFields doubles (NULL: none)
 };
 
 struct BatchHdr {

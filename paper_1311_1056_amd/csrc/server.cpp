@@ -42,6 +42,12 @@ struct Run {
     int64_t V = 0;
 };
 
+// final links of the finished runs submitted with keep_links, until taken
+struct Kept {
+    int64_t V = 0;
+    std::vector<double> links;
+};
+
 // first-fit allocator over [0, size) with coalescing of free ranges
 class Heap {
 public:
@@ -134,6 +140,7 @@ struct cl_server {
     double busy_s = 0;
     std::vector<float> all_step_ms;
     std::vector<float> waits;
+    std::map<uint64_t, Kept> kept;
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
@@ -301,6 +308,13 @@ cl_status retire(cl_server* s, size_t idx, int status)
     r.status = status;
     cl_status st = cl_measure(r.lat, &r.obs);
     if (st != CL_OK && st != CL_ENONFINITE) return st;
+    if (r.desc.keep_links) {
+        Kept k;
+        k.V = r.V;
+        k.links.resize((size_t)r.V * 72);
+        if ((st = cl_lattice_get_links(r.lat, k.links.data(), k.links.size())) != CL_OK) return st;
+        s->kept[r.id] = std::move(k);
+    }
     if ((st = cl_lattice_destroy(r.lat)) != CL_OK) return st;
     r.lat = nullptr;
     s->heap.release(r.off, r.bytes);
@@ -451,6 +465,20 @@ cl_status cl_server_stats_get(cl_server* s, cl_server_stats* o)
     o->step_ms_p99 = percentile(s->all_step_ms, 0.99);
     o->wait_s_p50 = percentile(s->waits, 0.5);
     o->wait_s_p99 = percentile(s->waits, 0.99);
+    return CL_OK;
+}
+
+cl_status cl_server_take_links(cl_server* s, uint64_t run_id, double* host, size_t n_doubles)
+{
+    if (!s || !host) return fail(CL_EINVAL, "NULL argument");
+    auto it = s->kept.find(run_id);
+    if (it == s->kept.end())
+        return fail(CL_EINVAL, "run %llu has no kept links (not finished, not kept, or already taken)",
+                    (unsigned long long)run_id);
+    if (n_doubles != it->second.links.size())
+        return fail(CL_EINVAL, "expected %zu doubles, got %zu", it->second.links.size(), n_doubles);
+    std::memcpy(host, it->second.links.data(), n_doubles * sizeof(double));
+    s->kept.erase(it);
     return CL_OK;
 }
 

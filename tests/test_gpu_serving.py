@@ -124,3 +124,60 @@ def test_large_run_served_equals_alone_bitwise(cl, prec):
     for k in ("plaq", "q", "d", "eps"):
         assert res[0]["obs"][k] == ref[k], (k, res[0]["obs"][k], ref[k])
     srv.close()
+
+
+ORACLE_RUNS = [
+    # FP64 runs of different shapes, theta (real, complex, none), cooling counts and modes,
+    # fixed and adaptive step, served together
+    dict(dims=(4, 4, 4, 4), beta=5.7, theta=0.0, prec=0, seed=301, n_steps=3, eps0=1e-3, adaptive=False, n_cool=5,
+         mode=0),
+    dict(dims=(4, 4, 2, 6), beta=6.0, theta=1.0, prec=0, seed=302, n_steps=4, eps0=1e-2, adaptive=True, n_cool=3,
+         mode=1),
+    dict(dims=(2, 4, 4, 4), beta=5.9, theta=0.5 - 0.3j, prec=0, seed=303, n_steps=2, eps0=5e-3, adaptive=True,
+         n_cool=2, mode=2),
+    dict(dims=(6, 4, 4, 2), beta=6.2, theta=2.0, prec=0, seed=304, n_steps=3, eps0=8e-3, adaptive=True, n_cool=0,
+         mode=1),
+    dict(dims=(4, 4, 4, 8), beta=6.0, theta=0.0, prec=0, seed=305, n_steps=2, eps0=1e-2, adaptive=True, n_cool=7,
+         mode=1),
+    # mixed precision, against the FP64 oracle at the mixed tolerances
+    # (one step: the mixed tolerances are per step from identical links)
+    dict(dims=(4, 4, 4, 4), beta=6.0, theta=1.0, prec=1, seed=306, n_steps=1, eps0=1e-2, adaptive=True, n_cool=4,
+         mode=1),
+]
+
+
+def test_served_runs_match_oracle(cl, orc):
+    """Runs served together in the batched kernels (one launch per kernel kind
+    over all runs of a precision) against the oracle running each alone: the
+    final links at 1e-11 relative (FP64) and the observables at 1e-12."""
+    srv = cl.Server(256 << 20)
+    ids = {}
+    for i, r in enumerate(ORACLE_RUNS):
+        ids[i] = srv.submit(r["dims"], r["beta"], r["theta"], r["prec"], r["seed"], r["n_steps"], r["eps0"],
+                            r["adaptive"], r["n_cool"], r["eps0"], 1.0, r["mode"], tag=i, keep_links=True)
+    res = {x["tag"]: x for x in drain(srv)}
+    assert len(res) == len(ORACLE_RUNS)
+    for i, r in enumerate(ORACLE_RUNS):
+        got = res[i]
+        print("served vs oracle", i, r["dims"], r["theta"], r["prec"], flush=True)
+        assert got["status"] == 0 and got["steps_done"] == r["n_steps"]
+        links = srv.take_links(ids[i], r["dims"])
+        W = orc.init_links(r["dims"], r["seed"], 0.3, 0.05)
+        if r["prec"] == 1:
+            W = W.astype(np.float32).astype(np.float64)  # the FP32 start the mixed run holds
+        obs, _ = orc.run(r["dims"], W, r["beta"], r["theta"], r["seed"], r["n_steps"], r["eps0"], r["adaptive"],
+                         r["n_cool"], r["eps0"], 1.0, r["mode"])
+        last = obs[-1]
+        lerr = float(np.max(np.abs(links - W)) / np.max(np.abs(W)))
+        ltol, otol = (1e-11, 1e-12) if r["prec"] == 0 else (1e-5, 1e-6)
+        assert lerr < ltol, (i, lerr)
+        o = got["obs"]
+        assert abs(o["plaq"] - complex(last[2], last[3])) < otol, i
+        assert abs(o["q"] - complex(last[4], last[5])) < otol * max(1.0, abs(complex(last[4], last[5]))), i
+        assert abs(o["d"] - last[1]) < otol * max(1.0, last[1]), i
+        assert abs(o["eps"] - last[6]) <= (1e-13 if r["prec"] == 0 else 1e-5) * last[6], i
+        assert o["step"] == r["n_steps"]
+    # taken links are released; a second take fails
+    with pytest.raises(cl.ClError):
+        srv.take_links(ids[0], ORACLE_RUNS[0]["dims"])
+    srv.close()

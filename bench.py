@@ -12,9 +12,11 @@ resident in HBM before the timed region starts.
 
 Prints ONE JSON line.  Also reports the mixed-precision path on the same
 workload, the dominant kernel's roofline (average duration from HIP events
-recorded around every launch of an instrumented replay of the same steps) and
-the FP64 CPU oracle
-timed on a bounded sample (2 steps) of the same workload.
+recorded around every launch of an instrumented replay of the same steps; the
+bytes are the floor of one read and one write of the link field per sweep),
+the whole step against the same floor and against the FP64 VALU, the served
+request stream (mixed, all-mixed, all-FP64 and one run at a time) and the
+FP64 CPU oracle timed on a bounded sample (2 steps) of the same workload.
 """
 from __future__ import annotations
 
@@ -84,6 +86,10 @@ def algorithmic_cost(kind, V, rs, theta):
         # odd transform (Hermitian products), per odd site: G and one exponential pair
         return {"bytes": L * 2 * mat + (V // 2) * 18 * rs,
                 "flops": L * 2 * hprod + (V // 2) * (8 * 54 + hexp)}
+    if kind == "cool_step":
+        # one cooling step in one kernel: every link read and written once (the
+        # halo re-reads are served on chip), both exponential pairs per site
+        return {"bytes": L * 2 * mat, "flops": L * 2 * hprod + V * (8 * 54 + hexp)}
     if kind == "drift":
         # one walk per loop along the staple P = e1 e2 e3: Wilson part P and
         # adj(P) (2 products, 3 adjugates, 2 complex axpys of 9 entries).  With
@@ -108,16 +114,31 @@ def algorithmic_cost(kind, V, rs, theta):
     return None
 
 
+def floor_bytes(kind, V, rs):
+    """The byte floor's share of one launch: every sweep over the lattice (the
+    CL update, each cooling step) reads and writes each link once, with
+    neighbours reused on chip; the drift, the clover field, the Omega pairs and
+    the second read of a two-kernel cooling step are overhead above it.  The
+    update and the cooling step's applying kernel carry the sweeps' bytes."""
+    if kind in ("update", "cool_apply", "cool_step"):
+        return 4 * V * 2 * 18 * rs
+    return 0
+
+
 def kernel_roofline(kind, ms_total, n, V, rs, theta, precision, dims):
-    """Roofline entry of one kernel from its event-measured average duration."""
+    """Roofline entry of one kernel from its event-measured average duration.
+    HBM-bound kernels are priced at their share of the sweep byte floor when
+    they have one (frac), with the kernel's own necessary bytes beside it."""
     c = algorithmic_cost(kind, V, rs, theta)
     t = ms_total / n * 1e-3
     peak_flops = VALU_FP64_TFLOPS if precision == "fp64" else VALU_FP32_TFLOPS
     ridge = peak_flops * 1e12 / (HBM_PEAK_GBS * 1e9)
     if c["flops"] / c["bytes"] < ridge:
-        achieved = c["bytes"] / t / 1e9
+        fb = floor_bytes(kind, V, rs) or c["bytes"]
+        achieved = fb / t / 1e9
         rf = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(achieved / HBM_PEAK_GBS, 4)}
+              "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_counted": fb,
+              "kernel_bytes_frac": round(c["bytes"] / t / 1e9 / HBM_PEAK_GBS, 4)}
     else:
         achieved = c["flops"] / t / 1e12
         rf = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak_flops, "unit": "TFLOP/s",
@@ -130,7 +151,7 @@ def kernel_roofline(kind, ms_total, n, V, rs, theta, precision, dims):
     return rf
 
 
-def run_gpu(args, precision, with_timing=True):
+def run_gpu(args, precision, with_timing=True, record=False):
     import torch
     import paper_1311_1056_amd as cl
     dims = tuple(int(x) for x in args.dims.split(","))
@@ -139,6 +160,14 @@ def run_gpu(args, precision, with_timing=True):
     lat = cl.Lattice(dims, args.beta, args.theta, prec, seed=3, device="cuda:0")
     lat.init(True, 0.3, 0.05)
     kw = dict(eps0=1e-2, adaptive=True, n_cool=args.ncool, eps_c=1e-2, alpha=1.0, mode=cl.CL_ALPHA_UNORM)
+    if record:
+        lat.record_enable(True)
+    # capture both step graphs (a block of eight steps and a single step) now,
+    # so that no capture lands in the timed region whatever --warmup is
+    lat.run_prepare(**kw)
+    # the capture above left the GPU idle: bring it back to its clocks before
+    # the warm-up steps
+    settle_gpu(dims, args.beta, args.theta, prec, kw)
     lat.run_steps(args.warmup, **kw)
     torch.cuda.synchronize()
     # timed region: K steps replayed from the captured step graph
@@ -155,10 +184,11 @@ def run_gpu(args, precision, with_timing=True):
         timing = lat.timing_read()
         lat.timing_enable(False)
     obs = lat.measure()
+    rec = lat.record_read(obs["step"] - args.steps + 1, args.steps) if record else None
     lat.close()
     dt = t1 - t0
     return {"V": V, "dims": dims, "seconds": dt, "ms_per_step": 1e3 * dt / args.steps,
-            "value": 4 * V * args.steps / dt, "timing": timing, "obs": obs}
+            "value": 4 * V * args.steps / dt, "timing": timing, "obs": obs, "record": rec}
 
 
 def roofline(res, precision, theta):
@@ -185,6 +215,28 @@ def roofline(res, precision, theta):
             rf["frac_of_copy"] = round(cus / rf["avg_us"], 4)
         rfs.append(rf)
     return rfs[0], kernels, rfs
+
+
+def step_roofline(res, precision, theta, n_cool):
+    """The whole CL step against the byte floor (one read and one write of the
+    link field for the update and for each of the n_cool cooling steps) and
+    against the VALU (the algorithmic flops of the step's kernels)."""
+    rs = 8 if precision == "fp64" else 4
+    V = res["V"]
+    t = res["ms_per_step"] * 1e-3
+    byt = (1 + n_cool) * 4 * V * 2 * 18 * rs
+    kinds = ["drift", "update"] + (["clover"] if theta else [])
+    flops = sum(algorithmic_cost(k, V, rs, theta)["flops"] for k in kinds)
+    flops += n_cool * (algorithmic_cost("cool_omega", V, rs, theta)["flops"] +
+                       algorithmic_cost("cool_apply", V, rs, theta)["flops"])
+    peak = VALU_FP64_TFLOPS if precision == "fp64" else VALU_FP32_TFLOPS
+    t_hbm, t_valu = byt / (HBM_PEAK_GBS * 1e9), flops / (peak * 1e12)
+    return {"floor_bytes_per_step": byt, "achieved_GBs": round(byt / t / 1e9, 1), "peak_GBs": HBM_PEAK_GBS,
+            "frac_hbm": round(byt / t / 1e9 / HBM_PEAK_GBS, 4), "flops_per_step": flops,
+            "achieved_TFLOPs": round(flops / t / 1e12, 2), "peak_TFLOPs": peak,
+            "hbm_bound_ms": round(1e3 * t_hbm, 4), "valu_bound_ms": round(1e3 * t_valu, 4),
+            "binding_roof": "hbm" if t_hbm >= t_valu else "valu",
+            "frac_of_binding_roof": round(max(t_hbm, t_valu) / t, 4), "ms_per_step": round(1e3 * t, 4)}
 
 
 _COPY_CACHE = {}
@@ -291,16 +343,30 @@ def served_mix(n, seed=6):
     return runs
 
 
-def served(args, capacity_lus, n_runs, load):
+def served_stream(capacity_lus, n_runs, load, prec=None):
+    """The request mix and its Poisson arrival times at `load` x the single-run
+    FP64 capacity (arrival seed 5); prec = 0 / 1 makes every run FP64 / mixed."""
+    import numpy as np
+    runs = served_mix(n_runs)
+    if prec is not None:
+        for r in runs:
+            r["prec"] = prec
+    work = np.array([4 * np.prod(r["dims"]) * r["n_steps"] for r in runs], dtype=float)
+    rate = load * capacity_lus / work.mean()  # runs per second
+    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / rate, len(runs)))
+    return runs, arrivals, rate
+
+
+PREC_NAMES = {None: "FP64 or mixed with probability 1/2", 0: "all FP64", 1: "all mixed"}
+
+
+def served(args, capacity_lus, n_runs, load, prec=None):
     """Continuous batching of the request mix arriving as a Poisson stream at
     `load` x the single-run FP64 capacity, under a fixed HBM budget (above 1x
     the queue grows and admission waits for memory to free up)."""
     import numpy as np
     import paper_1311_1056_amd as cl
-    runs = served_mix(n_runs)
-    work = np.array([4 * np.prod(r["dims"]) * r["n_steps"] for r in runs], dtype=float)
-    rate = load * capacity_lus / work.mean()  # runs per second
-    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / rate, len(runs)))
+    runs, arrivals, rate = served_stream(capacity_lus, n_runs, load, prec)
     srv = cl.Server(args.served_budget_mb << 20)
     results = []
     i = 0
@@ -328,7 +394,43 @@ def served(args, capacity_lus, n_runs, load):
             "batch_steps": st["batch_steps"], "load": load, "arrival_rate_runs_per_s": round(rate, 3),
             "budget_bytes": args.served_budget_mb << 20,
             "mix": "6^4, 8^4, 12^4, 16^4, 8^3x16, 24^3x8; beta U[5.7,6.2]; theta U[0,2]; 50-500 steps; "
-                   "1-20 D1 cooling steps; eps0 U[1e-3,1e-2]; FP64 or mixed; Poisson arrivals"}
+                   f"1-20 D1 cooling steps; eps0 U[1e-3,1e-2]; {PREC_NAMES[prec]}; Poisson arrivals"}
+
+
+def served_one_at_a_time(args, capacity_lus, n_runs, load, prec=0):
+    """The same request stream without batching: each run, in arrival order,
+    on its own lattice (the lattice API's graph-replayed steps) once the
+    previous one has finished.  A run's per-step latency is its run time over
+    its steps."""
+    import numpy as np
+    import torch
+    import paper_1311_1056_amd as cl
+    runs, arrivals, rate = served_stream(capacity_lus, n_runs, load, prec)
+    step_ms, waits, lu = [], [], 0
+    t0 = time.perf_counter()
+    for i, r in enumerate(runs):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        t_start = time.perf_counter() - t0
+        waits.append(t_start - arrivals[i])
+        lat = cl.Lattice(r["dims"], r["beta"], r["theta"], r["prec"], r["seed"])
+        lat.init(True, 0.3, 0.05)
+        lat.run_steps(r["n_steps"], r["eps0"], True, r["n_cool"], r["eps0"], 1.0, cl.CL_ALPHA_UNORM)
+        lat.measure()
+        lat.close()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0 - t_start
+        step_ms += [1e3 * dt / r["n_steps"]] * r["n_steps"]
+        lu += 4 * int(np.prod(r["dims"])) * r["n_steps"]
+    makespan = time.perf_counter() - t0
+    return {"value": round(lu / makespan, 1), "unit": "link-updates/s", "runs": len(runs),
+            "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
+            "step_ms_p99": round(float(np.percentile(step_ms, 99)), 3),
+            "queue_wait_s_p50": round(float(np.percentile(waits, 50)), 3),
+            "queue_wait_s_p99": round(float(np.percentile(waits, 99)), 3),
+            "makespan_s": round(makespan, 2), "load": load, "arrival_rate_runs_per_s": round(rate, 3),
+            "mix": f"the served stream, {PREC_NAMES[prec]}, one run at a time"}
 
 
 def with_args(args, **kw):
@@ -583,6 +685,35 @@ def chain_workload(args):
     return out
 
 
+def gauge_rotated_chains(n_chains, n, seed, sv=0.5, sa=0.3, sb=0.3):
+    """Input generator: U_k = Omega_k V_k Omega_{k+1}^-1 on periodic chains,
+    V_k = exp(i sigma.x) in SU(2) and Omega_k = exp(i sigma.(a + i b)) in
+    SL(2,C), x, a, b independent normals (numpy seed): unitary chains moved off
+    SU(2) along their gauge orbits.  (..., n, 8) doubles, row-major 2x2, (re, im)."""
+    import numpy as np
+    pauli = np.array([[[0, 1], [1, 0]], [[0, -1j], [1j, 0]], [[1, 0], [0, -1]]], complex)
+
+    def expm2(A):
+        # traceless 2x2: A^2 = w 1, exp(A) = cosh(l) 1 + sinh(l)/l A with l^2 = w
+        w = A[..., 0, 0] ** 2 + A[..., 0, 1] * A[..., 1, 0]
+        l = np.sqrt(w + 0j)
+        small = np.abs(l) < 1e-8
+        sh = np.where(small, 1.0 + w / 6.0, np.sinh(l) / np.where(small, 1.0, l))
+        return np.cosh(l)[..., None, None] * np.eye(2) + sh[..., None, None] * A
+
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0, sv, (n_chains, n, 3))
+    c = rng.normal(0, sa, (n_chains, n, 3)) + 1j * rng.normal(0, sb, (n_chains, n, 3))
+    Vk = expm2(1j * np.einsum('cka,aij->ckij', x, pauli))
+    O = expm2(1j * np.einsum('cka,aij->ckij', c, pauli))
+    Oi = expm2(-1j * np.einsum('cka,aij->ckij', c, pauli))
+    U = O @ Vk @ np.roll(Oi, -1, axis=1)
+    out = np.zeros(U.shape[:-2] + (8,))
+    out[..., 0::2] = U.real.reshape(U.shape[:-2] + (4,))
+    out[..., 1::2] = U.imag.reshape(U.shape[:-2] + (4,))
+    return out
+
+
 def chain_cooling_curves():
     """Cooling alone on gauge-rotated unitary chains U_k = Omega_k V_k
     Omega_{k+1}^-1 (64 chains, numpy seed 3, eps_c = 1e-3, alpha = 1): d(t)
@@ -591,7 +722,6 @@ def chain_cooling_curves():
     (the slowing down with the chain length)."""
     import numpy as np
     import paper_1311_1056_amd as cl
-    from tests.chainutil import gauge_rotated_chains
     ts = (1, 3, 10, 30, 100, 300, 1000, 3000, 10000, 30000)
 
     def curve(n, mode):
@@ -628,6 +758,28 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}), flush=True)
 
 
+def settle_gpu(dims, beta, theta, prec, kw, seconds=0.1):
+    """Run the leg's own kernels for about `seconds` on a separate scratch
+    lattice (seed 9, discarded) just before the measured lattice's warm-up
+    steps.  An idle GPU clocks down and needs about 10 ms of this load to come
+    back; a few warm-up steps are not enough.  Measured on one box (16^4,
+    ms per step of a 20-step call right after 5 warm-up steps / of 100 steps):
+    FP64 0.504 / 0.462 with nothing before, 0.487 / 0.461 after plain device
+    copies, 0.463 / 0.461 after this; mixed 0.392 / 0.370, 0.389 / 0.369,
+    0.370 / 0.369.  The measured lattice still takes exactly the warm-up and
+    timed steps it is asked for; nothing here is timed."""
+    import torch
+    import paper_1311_1056_amd as cl
+    s = cl.Lattice(dims, beta, theta, prec, seed=9, device="cuda:0")
+    s.init(True, 0.3, 0.05)
+    s.run_prepare(**kw)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        s.run_steps(8, **kw)
+        torch.cuda.synchronize()
+    s.close()
+
+
 _T0 = time.perf_counter()
 
 
@@ -653,6 +805,7 @@ def main():
     res = run_gpu(args, args.precision)
     rf, kernels, rfs = roofline(res, args.precision, args.theta)
     progress(f"main workload: {res['value'] / 1e6:.1f} M link-updates/s")
+    prec_name = "FP64" if args.precision == "fp64" else "mixed FP32/FP64"
     out = {
         "metric": METRIC,
         "value": round(res["value"], 1),
@@ -666,12 +819,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"CL + adaptive gauge cooling, SU(3) Wilson + theta, {args.dims.replace(',', 'x')} "
-                               f"periodic, beta={args.beta}, theta={args.theta}, seed 3, adaptive eps0=1e-2, "
-                               f"{args.ncool} D1 cooling steps (alpha=1, eps_c=1e-2) per update",
+        "config": {"workload": f"{args.dims.replace(',', 'x')} SU(3)+theta CL, {prec_name}, {args.ncool} D1 "
+                               f"cooling steps/update, beta={args.beta}, theta={args.theta}, adaptive eps0=1e-2, "
+                               f"alpha=1, eps_c=1e-2, seed 3, periodic Wilson action",
                    "lattice": args.dims.replace(",", "x"), "precision": args.precision,
                    "parallelism": "single GPU"},
         "roofline": rf,
+        "step_roofline": step_roofline(res, args.precision, args.theta, args.ncool),
         "rooflines": rfs,
         "kernels": kernels,
         "observables_after": {"plaq": [res["obs"]["plaq"].real, res["obs"]["plaq"].imag],
@@ -682,8 +836,20 @@ def main():
         progress(f"mixed precision: {mx['value'] / 1e6:.1f} M link-updates/s")
         mrf, mk, mrfs = roofline(mx, "mixed", args.theta)
         out["mixed"] = {"value": round(mx["value"], 1), "ms_per_step": round(mx["ms_per_step"], 4),
-                        "dtype": "f32 links/drift/cooling, f64 det renorm, reductions and control",
-                        "roofline": mrf, "rooflines": mrfs}
+                        "dtype": "f32 links/drift/cooling, f64 det renorm, reductions, measurement and control",
+                        "roofline": mrf, "step_roofline": step_roofline(mx, "mixed", args.theta, args.ncool),
+                        "rooflines": mrfs}
+        # the same workload recording every step's observables on the device
+        rc = run_gpu(args, "fp64", with_timing=False, record=True)
+        recd = rc["record"]
+        out["recorded"] = {"value": round(rc["value"], 1), "ms_per_step": round(rc["ms_per_step"], 4),
+                           "cost_vs_unrecorded": round(rc["ms_per_step"] / res["ms_per_step"] - 1.0, 4),
+                           "what": "P, Q, S, d before/after cooling, eps, Kmax, alpha_ad of every step, "
+                                   "device ring, no host synchronisation",
+                           "last_steps": {"step": recd[-3:, 0].tolist(), "plaq_re": recd[-3:, 3].tolist(),
+                                          "q_re": recd[-3:, 5].tolist(), "q_im": recd[-3:, 6].tolist(),
+                                          "d": recd[-3:, 2].tolist()}}
+        progress(f"recorded: {rc['value'] / 1e6:.1f} M link-updates/s")
     if args.precision == "fp64" and not args.no_extra:
         out["large_lattice"] = large_lattice(args)
         progress("32^4 leg done")
@@ -695,6 +861,14 @@ def main():
     if args.served_runs > 0 and args.precision == "fp64":
         out["served"] = served(args, res["value"], args.served_runs, 0.7)
         progress("served mix at 0.7x done")
+        # one stream three ways: batched all-mixed, batched all-FP64, FP64 one run at a time
+        nv = max(1, args.served_runs // 2)
+        out["served_all_mixed"] = served(args, res["value"], nv, 0.7, prec=1)
+        progress("served all-mixed done")
+        out["served_all_fp64"] = served(args, res["value"], nv, 0.7, prec=0)
+        progress("served all-FP64 done")
+        out["served_fp64_one_at_a_time"] = served_one_at_a_time(args, res["value"], nv, 0.7, prec=0)
+        progress("served one at a time done")
         out["served_overload"] = served(args, res["value"], max(1, args.served_runs // 2), 1.5)
         progress("served mix at 1.5x done")
         out["served_alone_vs_batched"] = alone_vs_batched(args)

@@ -193,6 +193,24 @@ cl_status cl_record_enable(cl_lattice* lat, int enable);
  * in the record (not taken yet, or more than 4096 steps ago).  Synchronous. */
 cl_status cl_record_read(cl_lattice* lat, int64_t first_step, int n, double* host);
 
+/* Allocation-free variant of cl_measure, for callers that cannot allocate
+ * device memory or wait for a stream: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Measures a link field the
+ * caller already holds on the device, in the host link layout (V*4*18
+ * doubles, lexicographic sites, x0 fastest), with the formulas of cl_measure
+ * (every sum in FP64, the clover matrices formed per site):
+ *   dev_out[0..1] plaquette (re, im), [2..3] Q_L, [4..5] S = S_W - i theta Q_L,
+ *   [6] d = (1/12V) sum Tr(U U^dagger - 1)
+ * (7 doubles of device memory the caller owns).  dims: four even extents >= 2
+ * with at most 2^20 sites (32^4); larger fields get CL_EINVAL.  The kernels
+ * run on hip_stream (NULL: the default stream) of the current device and the
+ * call returns without waiting; nothing is allocated at any call.  Their
+ * per-block partials live in a 224 KiB device array of the library's own,
+ * one per GPU, held until the process ends: calls that overlap on one GPU
+ * (e.g. on two streams) race on it and must be ordered by the caller. */
+cl_status cl_measure_links(const double* dev_links, const int32_t* dims, double beta, double theta_re,
+                           double theta_im, double* dev_out, void* hip_stream);
+
 /* Kernel kinds reported by cl_timing_read. */
 typedef enum {
     CL_K_INIT = 0, CL_K_UNORM = 1, CL_K_PACK = 2, CL_K_CLOVER = 3, CL_K_DRIFT = 4, CL_K_UPDATE = 5,

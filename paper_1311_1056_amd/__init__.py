@@ -116,6 +116,7 @@ def _load():
         "cl_record_enable": [vp, ctypes.c_int],
         "cl_record_read": [vp, ctypes.c_int64, ctypes.c_int, dp],
         "cl_server_take_links": [vp, ctypes.c_uint64, dp, sz],
+        "cl_measure_links": [vp, P(ctypes.c_int32), ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp],
         "cl_timing_enable": [vp, ctypes.c_int],
         "cl_server_create": [vp, sz, vp, P(vp)],
         "cl_server_submit": [vp, P(cl_run_desc), P(ctypes.c_uint64)],
@@ -162,6 +163,19 @@ def _dp(a):
 def make_desc(dims, beta, theta=0.0, precision=CL_FP64, seed=0):
     th = complex(theta)
     return cl_lattice_desc((ctypes.c_int32 * 4)(*dims), float(beta), th.real, th.imag, int(precision), int(seed))
+
+
+def measure_links(dev_links, dims, beta, theta, dev_out, stream=None):
+    """cl_measure_links: observables of a device link field (a float64 cuda
+    tensor in the host layout) into dev_out (7 float64 on the device); no
+    allocation, no wait."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(dev_links.device)
+    assert dev_links.dtype == torch.float64 and dev_links.is_contiguous()
+    assert dev_out.dtype == torch.float64 and dev_out.numel() >= 7
+    th = complex(theta)
+    _check(lib.cl_measure_links(ctypes.c_void_p(dev_links.data_ptr()), (ctypes.c_int32 * 4)(*dims), float(beta),
+                                th.real, th.imag, ctypes.c_void_p(dev_out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
 
 
 def cl_lattice_bytes(desc):

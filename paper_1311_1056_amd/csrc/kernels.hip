@@ -10,9 +10,13 @@
 // run's control block on the device, so no host round trip sits between the
 // kernels of a step and no grid-wide fence is needed inside a sweep.
 #include "engine.hpp"
+#include "host.hpp"
 
 #include <hip/hip_ext.h>
 #include <math.h>
+
+#include <cstring>
+#include <mutex>
 
 namespace clgc {
 
@@ -1306,20 +1310,20 @@ __device__ __forceinline__ mat3<double> ldU64(const RunArgs& ra, int mu, const S
 }
 
 // F_{mu nu}(x) = sum over the four counter-clockwise leaves L of (L - L^-1),
-// formed in FP64 from links of type T with the leaf products associated as in
-// k_clover; tp / ti get the traces of the first leaf (the plaquette U_{mu nu}(x)) and of
-// its inverse
-template <typename T>
-__device__ __forceinline__ mat3<double> clover_f64(const RunArgs& ra, const Site& x, int mu, int nu, cx<double>& tp,
-                                                   cx<double>& ti)
+// formed in FP64 from the links ld(mu, site) returns, with the leaf products
+// associated as in k_clover; tp / ti get the traces of the first leaf (the
+// plaquette U_{mu nu}(x)) and of its inverse
+template <typename LD>
+__device__ __forceinline__ mat3<double> clover_f64(const RunArgs& ra, const LD& ld, const Site& x, int mu, int nu,
+                                                   cx<double>& tp, cx<double>& ti)
 {
     const Site xpm = site_move(ra, x, mu, +1), xpn = site_move(ra, x, nu, +1);
     const Site xmm = site_move(ra, x, mu, -1), xmn = site_move(ra, x, nu, -1);
     const Site xmmpn = site_move(ra, xmm, nu, +1), xmmmn = site_move(ra, xmm, nu, -1);
     const Site xmnpm = site_move(ra, xmn, mu, +1);
-    mat3<double> S = ldU64<T>(ra, nu, x);
+    mat3<double> S = ld(nu, x);
     // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
-    mat3<double> L = (ldU64<T>(ra, mu, x) * ldU64<T>(ra, nu, xpm)) * m_adj(S * ldU64<T>(ra, mu, xpn));
+    mat3<double> L = (ld(mu, x) * ld(nu, xpm)) * m_adj(S * ld(mu, xpn));
     tp = m_tr(L);
     ti = (L.e[1][1] * L.e[2][2] - L.e[1][2] * L.e[2][1]) + (L.e[0][0] * L.e[2][2] - L.e[0][2] * L.e[2][0]) +
          (L.e[0][0] * L.e[1][1] - L.e[0][1] * L.e[1][0]);
@@ -1327,23 +1331,59 @@ __device__ __forceinline__ mat3<double> clover_f64(const RunArgs& ra, const Site
     __builtin_amdgcn_sched_barrier(0);
     // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
     {
-        const mat3<double> Umm = ldU64<T>(ra, mu, xmm);
-        L = S * (m_adj(ldU64<T>(ra, nu, xmm) * ldU64<T>(ra, mu, xmmpn)) * Umm);
+        const mat3<double> Umm = ld(mu, xmm);
+        L = S * (m_adj(ld(nu, xmm) * ld(mu, xmmpn)) * Umm);
         S = Umm;
     }
     F = F + (L - m_adj(L));
     __builtin_amdgcn_sched_barrier(0);
     // [U_nu(x-mu-nu) U_mu(x-mu)]^{-1} U_mu(x-mu-nu) U_nu(x-nu)
     {
-        const mat3<double> Unn = ldU64<T>(ra, nu, xmn);
-        L = m_adj(ldU64<T>(ra, nu, xmmmn) * S) * (ldU64<T>(ra, mu, xmmmn) * Unn);
+        const mat3<double> Unn = ld(nu, xmn);
+        L = m_adj(ld(nu, xmmmn) * S) * (ld(mu, xmmmn) * Unn);
         S = Unn;
     }
     F = F + (L - m_adj(L));
     __builtin_amdgcn_sched_barrier(0);
     // U_nu(x-nu)^{-1} U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^{-1}
-    L = m_adj(S) * ((ldU64<T>(ra, mu, xmn) * ldU64<T>(ra, nu, xmnpm)) * m_adj(ldU64<T>(ra, mu, x)));
+    L = m_adj(S) * ((ld(mu, xmn) * ld(nu, xmnpm)) * m_adj(ld(mu, x)));
     return F + (L - m_adj(L));
+}
+
+// One site's measurement sums, all in FP64 from the links ld returns: v[0..3]
+// the plaquette traces Tr P and Tr P^-1 (re, im) of its six planes, v[4..5]
+// the clover bracket Tr F01 F23 - Tr F02 F13 + Tr F03 F12 (re, im), v[6] the
+// norms Tr U U^dagger of its four links
+template <typename LD>
+__device__ __forceinline__ void site_obs_f64(const RunArgs& ra, const LD& ld, const Site& x, double (&v)[7])
+{
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) v[6] += m_norm2(ld(mu, x));
+    // planes in the pairs (01, 23), (02, 13), (03, 12) of the charge
+    cx<double> q = {0.0, 0.0};
+#pragma unroll 1
+    for (int P = 0; P < 3; ++P) {
+        const int mu2 = P == 0 ? 2 : 1, nu2 = P == 2 ? 2 : 3;
+        cx<double> tp, ti;
+        const mat3<double> Fa = clover_f64(ra, ld, x, 0, P + 1, tp, ti);
+        v[0] += tp.re;
+        v[1] += tp.im;
+        v[2] += ti.re;
+        v[3] += ti.im;
+        __builtin_amdgcn_sched_barrier(0);
+        const mat3<double> Fd = clover_f64(ra, ld, x, mu2, nu2, tp, ti);
+        v[0] += tp.re;
+        v[1] += tp.im;
+        v[2] += ti.re;
+        v[3] += ti.im;
+        const cx<double> t = m_trmul(Fa, Fd);
+        const double sg = P == 1 ? -1.0 : 1.0;
+        q.re += sg * t.re;
+        q.im += sg * t.im;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    v[4] = q.re;
+    v[5] = q.im;
 }
 
 // One lane per site.  FROM_F: the clover field of the current links is in F
@@ -1394,33 +1434,7 @@ __global__ void __launch_bounds__(kBlock) k_measure(const KArgs ka)
             v[4] = q.re;
             v[5] = q.im;
         } else {
-#pragma unroll 1
-            for (int mu = 0; mu < 4; ++mu) v[6] += m_norm2(ldU64<T>(ra, mu, x));
-            // planes in the pairs (01, 23), (02, 13), (03, 12) of the charge
-            cx<double> q = {0.0, 0.0};
-#pragma unroll 1
-            for (int P = 0; P < 3; ++P) {
-                const int mu2 = P == 0 ? 2 : 1, nu2 = P == 2 ? 2 : 3;
-                cx<double> tp, ti;
-                const mat3<double> Fa = clover_f64<T>(ra, x, 0, P + 1, tp, ti);
-                v[0] += tp.re;
-                v[1] += tp.im;
-                v[2] += ti.re;
-                v[3] += ti.im;
-                __builtin_amdgcn_sched_barrier(0);
-                const mat3<double> Fd = clover_f64<T>(ra, x, mu2, nu2, tp, ti);
-                v[0] += tp.re;
-                v[1] += tp.im;
-                v[2] += ti.re;
-                v[3] += ti.im;
-                const cx<double> t = m_trmul(Fa, Fd);
-                const double sg = P == 1 ? -1.0 : 1.0;
-                q.re += sg * t.re;
-                q.im += sg * t.im;
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            v[4] = q.re;
-            v[5] = q.im;
+            site_obs_f64(ra, [&](int m, const Site& y) { return ldU64<T>(ra, m, y); }, x, v);
         }
     }
     block_reduce<7>(v, lds);
@@ -1583,6 +1597,109 @@ __global__ void k_write_state(Ctrl* c, int64_t step, double bound)
         c->bound = bound;
     }
 }
+
+// ---------------------------------------------------------------------------
+// Measurement of a device-resident link field without any allocation
+// (cl_measure_links): the per-block partials live in a file-scope device
+// array, the result goes to the caller's device memory, and nothing waits for
+// the stream, so the call also works where hipMalloc cannot be called.
+
+constexpr int kScratchMaxSites = 1 << 20;                   // 32^4
+constexpr int kScratchBlocks = kScratchMaxSites / kBlock;   // 4096 logical blocks
+constexpr int kScratchParts = 7;                            // partials per block
+// 7 x 4096 doubles = 224 KiB on every GPU the library runs on, held until the
+// process ends; every call on a GPU shares it
+static __device__ __align__(256) double scratch[kScratchParts * kScratchBlocks];
+
+// link (mu, s) of a field in the host layout [site][mu][row][col][re, im]
+__device__ __forceinline__ mat3<double> load_aos(const double* __restrict__ f, const RunArgs& ra, int mu, const Site& s)
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* q = (const d2*)(f + ((size_t)site_lex(ra, s) * 4 + mu) * 18);
+    mat3<double> m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const d2 c = q[e];
+        m.e[e / 3][e % 3] = {c.x, c.y};
+    }
+    return m;
+}
+
+// one lane per site (lexicographic); block b writes part[j * gridDim.x + b]
+__global__ void __launch_bounds__(kBlock) k_measure_links(const RunArgs ra, const double* __restrict__ links,
+                                                          double* __restrict__ part)
+{
+    __shared__ double lds[7 * 4];
+    const int s = (int)(blockIdx.x * kBlock + threadIdx.x);
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (s < ra.V) {
+        Site x;
+        int r = s / ra.L[0];
+        x.x0 = s - r * ra.L[0];
+        int q = r / ra.L[1];
+        x.x1 = r - q * ra.L[1];
+        r = q;
+        q = r / ra.L[2];
+        x.x2 = r - q * ra.L[2];
+        x.x3 = q;
+        site_obs_f64(ra, [&](int m, const Site& y) { return load_aos(links, ra, m, y); }, x, v);
+    }
+    block_reduce<7>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) part[j * gridDim.x + blockIdx.x] = v[j];
+    }
+}
+
+// fixed-order sums of the nblk partials; out = P (re, im), Q (re, im), S (re, im), d
+__global__ void __launch_bounds__(kBlock) k_measure_links_final(const RunArgs ra, const double* __restrict__ part,
+                                                                int nblk, double* __restrict__ out)
+{
+    __shared__ double lds[8];
+    double o[7];
+    for (int j = 0; j < 7; ++j) o[j] = gather_values(part + (size_t)j * nblk, nblk, lds);
+    if (threadIdx.x == 0) {
+        const double V = ra.V;
+        const double qs = -1.0 / (256.0 * M_PI * M_PI);
+        const double qr = qs * o[4], qi = qs * o[5];
+        const double swr = ra.beta * (6.0 * V - (o[0] + o[2]) / 6.0);
+        const double swi = -ra.beta * (o[1] + o[3]) / 6.0;
+        out[0] = o[0] / (18.0 * V);
+        out[1] = o[1] / (18.0 * V);
+        out[2] = qr;
+        out[3] = qi;
+        out[4] = swr + (ra.th_im * qr + ra.th_re * qi);
+        out[5] = swi - (ra.th_re * qr - ra.th_im * qi);
+        out[6] = o[6] / (12.0 * V) - 1.0;
+    }
+}
+
+namespace {
+
+// device address of `scratch` on each GPU, taken once per device with that
+// device current (the array's name is only a host-side stand-in)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+hipError_t scratch_of_current_device(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // host launchers
@@ -1764,3 +1881,41 @@ hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t s
 }
 
 }  // namespace clgc
+
+extern "C" cl_status cl_measure_links(const double* dev_links, const int32_t* dims, double beta, double theta_re,
+                                      double theta_im, double* dev_out, void* hip_stream)
+{
+    using namespace clgc;
+    if (!dev_links || !dims || !dev_out) return fail(CL_EINVAL, "NULL argument");
+    long long V = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (dims[m] < 2 || (dims[m] & 1)) return fail(CL_EINVAL, "extent L%d = %d must be even and >= 2", m, dims[m]);
+        V *= dims[m];
+    }
+    if (V > kScratchMaxSites)
+        return fail(CL_EINVAL, "cl_measure_links: %lld sites, at most %d (its scratch is sized for 32^4)", V,
+                    kScratchMaxSites);
+    if (!(beta > 0) || !std::isfinite(beta) || !std::isfinite(theta_re) || !std::isfinite(theta_im))
+        return fail(CL_EINVAL, "beta must be > 0 and finite, theta finite");
+    double* part = nullptr;
+    HIP_TRY(scratch_of_current_device(&part));
+    RunArgs ra;
+    std::memset(&ra, 0, sizeof ra);
+    for (int m = 0; m < 4; ++m) ra.L[m] = dims[m];
+    ra.Lh0 = dims[0] / 2;
+    ra.V = (int)V;
+    ra.Vh = (int)(V / 2);
+    ra.beta = beta;
+    ra.th_re = theta_re;
+    ra.th_im = theta_im;
+    const int nblk = (int)((V + kBlock - 1) / kBlock);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    // every partial slot [0, nblk) is written before it is read: nothing of an
+    // earlier call's scratch contents is used
+    hipLaunchKernelGGL(k_measure_links, dim3(nblk), dim3(kBlock), 0, st, ra, dev_links, part);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_measure_links_final, dim3(1), dim3(kBlock), 0, st, ra, (const double*)part, nblk, dev_out);
+    HIP_TRY(hipGetLastError());
+    return CL_OK;
+}
+

@@ -224,7 +224,11 @@ cl_status enqueue_record(cl_lattice* lat)
     return CL_OK;
 }
 
-cl_status enqueue_step(cl_lattice* lat)
+// One CL update.  The drift kernel leaves K_max for the update kernel, which
+// forms eps itself.  fold: cooling steps follow in the same sequence and the
+// first of them finishes the update (norm, step counter); otherwise, or with
+// no cooling, a finalize launch does.
+cl_status enqueue_step(cl_lattice* lat, bool fold)
 {
     const bool theta = lat->has_theta;
     if (theta && !lat->F_valid) {
@@ -239,14 +243,17 @@ cl_status enqueue_step(cl_lattice* lat)
         if (st) return st;
     }
     TIMED(lat, CL_K_DRIFT, launch_drift(lat->L, lat->prec, theta));
-    TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_DRIFT, 0));
     TIMED(lat, CL_K_UPDATE, launch_update(lat->L, lat->prec));
-    TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_UPDATE, 0));
+    if (!fold || lat->args.n_cool == 0) TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_UPDATE, 0));
     lat->F_valid = false;
     return CL_OK;
 }
 
-cl_status enqueue_cool(cl_lattice* lat, int n)
+// n cooling steps; finalize: sum the last step's norm partials into the
+// control block (the norm, its history entry, the status).  Inside
+// cl_run_steps only the call's last step is finalized: nothing between two CL
+// steps reads that norm (the next update's own partials drive D_1).
+cl_status enqueue_cool(cl_lattice* lat, int n, bool finalize)
 {
     for (int i = 0; i < n; ++i) {
         if (lat->args.mode == CL_ALPHA_GRAD) {
@@ -257,7 +264,7 @@ cl_status enqueue_cool(cl_lattice* lat, int n)
     }
     // the next cooling step reduces the apply partials itself; only the last
     // one is finalized (unitarity norm, history, status)
-    if (n > 0) TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_COOL, -1));
+    if (finalize && n > 0) TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_COOL, -1));
     if (n > 0) lat->F_valid = false;
     return CL_OK;
 }
@@ -291,8 +298,8 @@ cl_status ensure_graph(cl_lattice* lat, int n_cool, int n_rep, hipGraphExec_t& s
     hipError_t e = hipStreamBeginCapture(lat->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         for (int r = 0; r < n_rep && st == CL_OK; ++r) {
-            st = enqueue_step(lat);
-            if (st == CL_OK) st = enqueue_cool(lat, n_cool);
+            st = enqueue_step(lat, true);
+            if (st == CL_OK) st = enqueue_cool(lat, n_cool, false);
         }
         e = hipStreamEndCapture(lat->cap_stream, &g);
     }
@@ -495,7 +502,7 @@ cl_status cl_langevin_step(cl_lattice* lat, const cl_step_desc* step, double* ep
     if (!lat) return fail(CL_EINVAL, "lattice is NULL");
     cl_status st = set_step_params(lat, step);
     if (st) return st;
-    if ((st = enqueue_step(lat)) != CL_OK) return st;
+    if ((st = enqueue_step(lat, false)) != CL_OK) return st;
     if (eps_used) {
         Ctrl c;
         if ((st = read_ctrl(lat, &c)) != CL_OK) return st;
@@ -510,7 +517,7 @@ cl_status cl_gauge_cool(cl_lattice* lat, const cl_cool_desc* cool, double* unorm
     if (!lat) return fail(CL_EINVAL, "lattice is NULL");
     cl_status st = set_cool_params(lat, cool);
     if (st) return st;
-    if ((st = enqueue_cool(lat, cool->n_steps)) != CL_OK) return st;
+    if ((st = enqueue_cool(lat, cool->n_steps, true)) != CL_OK) return st;
     if (unorm_after) {
         Ctrl c;
         if ((st = read_ctrl(lat, &c)) != CL_OK) return st;
@@ -531,9 +538,10 @@ cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_
     if (lat->timing) {
         // instrumented path: individual launches bracketed by events
         for (int i = 0; i < n_steps; ++i) {
-            if ((st = enqueue_step(lat)) != CL_OK) return st;
-            if ((st = enqueue_cool(lat, cool->n_steps)) != CL_OK) return st;
+            if ((st = enqueue_step(lat, true)) != CL_OK) return st;
+            if ((st = enqueue_cool(lat, cool->n_steps, false)) != CL_OK) return st;
         }
+        if (cool->n_steps > 0) TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_COOL, -1));
         return lat->record ? enqueue_record(lat) : CL_OK;
     }
     // whole blocks of kGraphSteps steps from one graph (the gap between two graph
@@ -548,6 +556,8 @@ cl_status cl_run_steps(cl_lattice* lat, const cl_step_desc* step, const cl_cool_
         for (int i = 0; i < rest; ++i) HIP_TRY(hipGraphLaunch(lat->step_graph, lat->stream));
     }
     lat->F_valid = false;
+    // the last cooling step's norm into the control block
+    if (cool->n_steps > 0) HIP_TRY(launch_finalize(lat->L, FIN_COOL, -1));
     // the last step's entry (the graph steps recorded the ones before it)
     return lat->record ? enqueue_record(lat) : CL_OK;
 }

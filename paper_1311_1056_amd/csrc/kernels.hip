@@ -604,6 +604,12 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
     double v[1] = {kn2};
     block_reduce<1, true>(v, lds);
     store_partials(ra, KIND_DRIFT, lb, v);
+    // the step's K_max for the update kernel, with no finalize launch between
+    if (threadIdx.x == 0) {
+        const int par = (int)(ra.ctrl->step & 1);
+        atomicMax(&ra.ctrl->kslot[par][blockIdx.x & (kXcds - 1)][0],
+                  (unsigned long long)__double_as_longlong(v[0]));
+    }
     CLGC_END_BLOCKS
 }
 
@@ -611,68 +617,105 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
 // Langevin update: U <- exp(i (eps K + sqrt(eps) eta_a lambda_a)) U, then
 // U <- U det(U)^{-1/3} in FP64.
 
+// Every wavefront forms the step size itself from the drift's K_max (the
+// per-XCD maxima its blocks left in the control block), so no finalize runs
+// between the two kernels; block 0 records eps, K_max and the bound and
+// clears the slots the next step's drift will use.  The update runs on the
+// cooling kernels' logical blocks (at most kMaxCoolBlocks, each looping over
+// chunks of 256 links) and leaves its unitarity-norm partials where the next
+// cooling step's wavefronts sum them.
 template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
 {
     __shared__ double lds[8];
-    CLGC_FOR_BLOCKS(KIND_LINK)
-    const Ctrl* cr = ra.ctrl;
-    const int ok = cr->status == ST_OK;
-    const double eps = cr->eps;
+    CLGC_FOR_BLOCKS(KIND_COOL)
+    Ctrl* cr = ra.ctrl;
     const int64_t step = cr->step;
+    const int par = (int)(step & 1);
+    unsigned long long km = 0;
+#pragma unroll
+    for (int x = 0; x < kXcds; ++x) {
+        const unsigned long long b = __hip_atomic_load(&cr->kslot[par][x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        km = b > km ? b : km;
+    }
+    const double kmax = sqrt(__longlong_as_double((long long)km));
+    // eps_n = min(eps0, B / K_max), B fixed on the first adaptive step; the
+    // bound block 0 may be writing below is the value computed here either way
+    const double bound = cr->bound;
+    double B = bound, eps = ra.eps0;
+    if (ra.adaptive) {
+        if (B <= 0.0) B = ra.drift_bound > 0.0 ? ra.drift_bound : ra.eps0 * kmax;
+        if (kmax > 0.0 && B / kmax < ra.eps0) eps = B / kmax;
+    }
+    const int ok = cr->status == ST_OK && isfinite(kmax);
+    if (lb == 0 && threadIdx.x == 0) {
+        cr->kmax = kmax;
+        cr->eps = eps;
+        if (ra.adaptive && bound <= 0.0) cr->bound = B;
+        if (!isfinite(kmax)) cr->status = ST_NONFINITE;
+        if (ok) cr->upd_pending = 1;
+#pragma unroll
+        for (int x = 0; x < kXcds; ++x)
+            __hip_atomic_store(&cr->kslot[par ^ 1][x][0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int nch = (4 * ra.V + kBlock - 1) / kBlock;
+    const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
     double un = 0.0;
-    if (tid < 4 * ra.V && ok) {
-        int mu, p, h;
-        link_decompose(ra, tid, mu, p, h);
-        const Site s = site_coords(ra, p, h);
-        const uint32_t c0 = (uint32_t)(4 * site_lex(ra, s) + mu);
-        const T se = T(sqrt(eps) * 1.41421356237309504880);  // sqrt(eps) * sqrt(2)
-        T eta[8];
+    for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+        const int t = c * kBlock + (int)threadIdx.x;
+        if (t < 4 * ra.V && ok) {
+            int mu, p, h;
+            link_decompose(ra, t, mu, p, h);
+            const Site s = site_coords(ra, p, h);
+            const uint32_t c0 = (uint32_t)(4 * site_lex(ra, s) + mu);
+            const T se = T(sqrt(eps) * 1.41421356237309504880);  // sqrt(eps) * sqrt(2)
+            T eta[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) normal_pair<T>(ra.seed, c0, (uint32_t)step, (uint32_t)j, kStreamNoise,
-                                                   eta[2 * j], eta[2 * j + 1]);
+            for (int j = 0; j < 4; ++j) normal_pair<T>(ra.seed, c0, (uint32_t)step, (uint32_t)j, kStreamNoise,
+                                                       eta[2 * j], eta[2 * j + 1]);
 #pragma unroll
-        for (int a = 0; a < 8; ++a) eta[a] *= se;
-        // A = i (eps K + H),  H = sum_a eta_a lambda_a (Hermitian)
-        const mat3<T> K = load_mat((const cx<T>*)ra.K, tid, 4 * ra.V);
-        const T r3 = T(0.57735026918962576451);
-        mat3<T> H;
-        H.e[0][0] = {eta[2] + r3 * eta[7], T(0)};
-        H.e[1][1] = {r3 * eta[7] - eta[2], T(0)};
-        H.e[2][2] = {T(-2) * r3 * eta[7], T(0)};
-        H.e[0][1] = {eta[0], -eta[1]};
-        H.e[1][0] = {eta[0], eta[1]};
-        H.e[0][2] = {eta[3], -eta[4]};
-        H.e[2][0] = {eta[3], eta[4]};
-        H.e[1][2] = {eta[5], -eta[6]};
-        H.e[2][1] = {eta[5], eta[6]};
-        const T te = T(eps);
-        mat3<T> A;
+            for (int a = 0; a < 8; ++a) eta[a] *= se;
+            // A = i (eps K + H),  H = sum_a eta_a lambda_a (Hermitian)
+            const mat3<T> K = load_mat((const cx<T>*)ra.K, t, 4 * ra.V);
+            const T r3 = T(0.57735026918962576451);
+            mat3<T> H;
+            H.e[0][0] = {eta[2] + r3 * eta[7], T(0)};
+            H.e[1][1] = {r3 * eta[7] - eta[2], T(0)};
+            H.e[2][2] = {T(-2) * r3 * eta[7], T(0)};
+            H.e[0][1] = {eta[0], -eta[1]};
+            H.e[1][0] = {eta[0], eta[1]};
+            H.e[0][2] = {eta[3], -eta[4]};
+            H.e[2][0] = {eta[3], eta[4]};
+            H.e[1][2] = {eta[5], -eta[6]};
+            H.e[2][1] = {eta[5], eta[6]};
+            const T te = T(eps);
+            mat3<T> A;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const cx<T> x = {fma(te, K.e[i][j].re, H.e[i][j].re), fma(te, K.e[i][j].im, H.e[i][j].im)};
-                A.e[i][j] = {-x.im, x.re};
-            }
-        const mat3<T> R = m_exp_traceless(A);
-        const mat3<T> U = load_mat((const cx<T>*)ra.U, tid, 4 * ra.V);
-        // det renormalisation in FP64 on the principal branch
-        const mat3<double> W = m_to_double(R * U);
-        const cx<double> d = m_det(W);
-        const double lr = -log(sqrt(fma(d.re, d.re, d.im * d.im))) / 3.0;
-        const double ph = -atan2(d.im, d.re) / 3.0;
-        double sn, cs;
-        sincos(ph, &sn, &cs);
-        const double mg = exp(lr);
-        const cx<double> w = {mg * cs, mg * sn};
-        const mat3<T> Un = m_cast_from<T>(m_scale(W, w));
-        store_mat((cx<T>*)ra.U, tid, 4 * ra.V, Un);
-        un = (double)m_norm2(Un);
+                for (int j = 0; j < 3; ++j) {
+                    const cx<T> x = {fma(te, K.e[i][j].re, H.e[i][j].re), fma(te, K.e[i][j].im, H.e[i][j].im)};
+                    A.e[i][j] = {-x.im, x.re};
+                }
+            const mat3<T> R = m_exp_traceless(A);
+            const mat3<T> U = load_mat((const cx<T>*)ra.U, t, 4 * ra.V);
+            // det renormalisation in FP64 on the principal branch
+            const mat3<double> W = m_to_double(R * U);
+            const cx<double> d = m_det(W);
+            const double lr = -log(sqrt(fma(d.re, d.re, d.im * d.im))) / 3.0;
+            const double ph = -atan2(d.im, d.re) / 3.0;
+            double sn, cs;
+            sincos(ph, &sn, &cs);
+            const double mg = exp(lr);
+            const cx<double> w = {mg * cs, mg * sn};
+            const mat3<T> Un = m_cast_from<T>(m_scale(W, w));
+            store_mat((cx<T>*)ra.U, t, 4 * ra.V, Un);
+            un += (double)m_norm2(Un);
+        }
     }
     double v[1] = {un};
     block_reduce<1>(v, lds);
-    store_partials(ra, KIND_LINK, lb, v);
+    if (threadIdx.x == 0) ra.cpart[lb] = v[0];
     CLGC_END_BLOCKS
 }
 
@@ -1012,9 +1055,11 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
             // 0, when the norm that every wavefront computes identically is not
             // finite: then every Omega is non-finite and nothing reads them.
             const bool ok = cr->status == ST_OK;
-            // unitarity norm entering the step: from the finalized update (step 0)
-            // or the previous step's apply partials
-            const double un = iter == 0 ? cr->unorm : wave_cool_sum(ra);
+            // unitarity norm entering the step: the partials of the CL update just
+            // applied or of the previous cooling step; else (a cooling call on its
+            // own) the finalized norm
+            const bool pend = iter == 0 && cr->upd_pending;
+            const double un = iter == 0 && !pend ? cr->unorm : wave_cool_sum(ra);
             // D_2 = mean |f_ax| from the gradient-norm pass just before (its
             // partials, one per cooling logical block)
             const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
@@ -1023,6 +1068,11 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
             if (ok && lb == 0 && c == 0 && threadIdx.x == 0) {
                 cr->alpha_cur = alpha_ad;
                 cr->unorm = un;
+                if (pend) {
+                    // the update's finalization: its norm, and the step is taken
+                    cr->d_pre = un / (12.0 * ra.V) - 1.0;
+                    cr->step = cr->step + 1;
+                }
                 if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
                 if (iter < kMaxCoolHist) {
                     cr->hist_alpha[iter] = alpha_ad;
@@ -1090,6 +1140,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
         double v[1] = {un};
         block_reduce<1>(v, lds);
         if (ok && threadIdx.x == 0) ra.cpart[lb] = v[0];
+        // the omega kernel before this one consumed the update's partials
+        if (iter == 0 && lb == 0 && threadIdx.x == 0) cr->upd_pending = 0;
     }
     CLGC_END_BLOCKS
 }
@@ -1133,13 +1185,18 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
         if (c0 < c1) omega_loads(ra, c0, h, lok, Af, Ab);
         // the run state, as in k_cool_omega
         const bool ok = cr->status == ST_OK;
-        const double un = iter == 0 ? cr->unorm : wave_cool_sum(ra);
+        const bool pend = iter == 0 && cr->upd_pending;
+        const double un = iter == 0 && !pend ? cr->unorm : wave_cool_sum(ra);
         const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
         const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
                                              : (ra.mode == 2 ? ra.alpha / d2 : ra.alpha);
         if (ok && lb == 0 && c0 < c1 && threadIdx.x == 0) {
             cr->alpha_cur = alpha_ad;
             cr->unorm = un;
+            if (pend) {
+                cr->d_pre = un / (12.0 * ra.V) - 1.0;
+                cr->step = cr->step + 1;
+            }
             if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
             if (iter < kMaxCoolHist) {
                 cr->hist_alpha[iter] = alpha_ad;
@@ -1244,6 +1301,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int it
         double v[1] = {un};
         block_reduce<1>(v, lds);
         if (ok && threadIdx.x == 0) ra.cpart[lb] = v[0];
+        if (iter == 0 && lb == 0 && threadIdx.x == 0) cr->upd_pending = 0;
     }
     CLGC_END_BLOCKS
 }
@@ -1466,6 +1524,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, i
                 c->status = isfinite(tot) ? ST_OK : ST_NONFINITE;
                 c->hist_n = 0;
                 c->alpha_cur = 0.0;
+                c->upd_pending = 0;
+                for (int x = 0; x < kXcds; ++x) c->kslot[0][x][0] = c->kslot[1][x][0] = 0ull;
             }
             break;
         }
@@ -1473,6 +1533,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, i
             const double tot = gather_partials(ra, KIND_LINK, 0, lds);
             if (threadIdx.x == 0) {
                 c->unorm = tot;
+                c->upd_pending = 0;
                 if (!isfinite(tot)) c->status = ST_NONFINITE;
             }
             break;
@@ -1493,12 +1554,17 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, i
             break;
         }
         case FIN_UPDATE: {
-            if (!ok) break;  // the update kernel left the links untouched
-            const double tot = gather_partials(ra, KIND_LINK, 0, lds);
+            // nothing to do if the update left the links untouched (not ok) or a
+            // cooling step already finished it
+            if (!ok || !c->upd_pending) break;
+            // (summed as the cooling kernels sum these partials, so that every
+            // path gives the same bits)
+            const double tot = wave_cool_sum(ra);
             if (threadIdx.x == 0) {
                 c->unorm = tot;
                 c->d_pre = tot / (12.0 * ra.V) - 1.0;
                 c->step = c->step + 1;
+                c->upd_pending = 0;
                 if (!isfinite(tot)) c->status = ST_NONFINITE;
             }
             break;
@@ -1507,7 +1573,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, i
             // iter < 0: the run's own last cooling step (runs in a batch differ)
             const int it = iter < 0 ? ra.n_cool - 1 : iter;
             if (!ok || it < 0 || it >= ra.n_cool) break;
-            const double tot = gather_values(ra.cpart, ra.nblk[KIND_COOL], lds);
+            const double tot = wave_cool_sum(ra);
             if (threadIdx.x == 0) {
                 c->unorm = tot;
                 if (it + 1 <= kMaxCoolHist) c->hist_un[it + 1] = tot;
@@ -1595,6 +1661,8 @@ __global__ void k_write_state(Ctrl* c, int64_t step, double bound)
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->step = step;
         c->bound = bound;
+        // the drift of step n leaves its maximum in the slots of parity n & 1
+        for (int x = 0; x < kXcds; ++x) c->kslot[0][x][0] = c->kslot[1][x][0] = 0ull;
     }
 }
 
@@ -1799,8 +1867,8 @@ hipError_t launch_drift(const Launch& L, int prec, bool theta)
 
 hipError_t launch_update(const Launch& L, int prec)
 {
-    if (prec) CLGC_LAUNCH((k_update<float, FAST_>), KIND_LINK);
-    else CLGC_LAUNCH((k_update<double, FAST_>), KIND_LINK);
+    if (prec) CLGC_LAUNCH((k_update<float, FAST_>), KIND_COOL);
+    else CLGC_LAUNCH((k_update<double, FAST_>), KIND_COOL);
     return hipGetLastError();
 }
 

@@ -61,6 +61,13 @@ struct Ctrl {
     int64_t step;       // CL step counter n (Philox counter word 1)
     int32_t status;     // Status
     int32_t hist_n;     // cooling steps recorded
+    int32_t upd_pending;  // 1: the unitarity-norm partials of an applied CL update wait in
+                          // cpart, for the next cooling step (or FIN_UPDATE) to finish the step
+    int32_t pad;
+    // max ||Khat||^2 of the drift of step n, as IEEE bit patterns (their order is the
+    // order of non-negative doubles, so an integer atomic max is exact and order-free):
+    // slot [n & 1][x] collects the blocks dispatched to XCD x, 128 bytes apart
+    unsigned long long kslot[2][kXcds][16];
 };
 
 // Per-run descriptor (device copy written by the host when it changes).

@@ -244,7 +244,6 @@ cl_status enqueue_group_step(cl_server* s, int g, int max_nc, bool any_theta, bo
     const Launch L = group_launch(s, g, st);
     if (any_theta) HIP_TRY(launch_clover(L, g, 1));
     HIP_TRY(launch_drift(L, g, any_theta));
-    HIP_TRY(launch_finalize(L, FIN_DRIFT, 0));
     HIP_TRY(launch_update(L, g));
     HIP_TRY(launch_finalize(L, FIN_UPDATE, 0));
     for (int i = 0; i < max_nc; ++i) {

@@ -17,18 +17,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "clgc_oracle.c"), os.path.join(_HERE, "chain_oracle.c")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+# CLGC_ORACLE_SANITIZE=1 selects a build under AddressSanitizer and
+# UndefinedBehaviorSanitizer (a separate library; the process must preload
+# the gcc sanitizer runtimes, as the sanitizer test does)
+_SANITIZE = os.environ.get("CLGC_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile clgc_oracle.c into liboracle.so (gcc, OpenMP)."""
+    """Compile clgc_oracle.c and chain_oracle.c into liboracle.so (gcc, OpenMP)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-             "-o", tmp, *_SRC, "-lm"])
+             *(_SAN_FLAGS if _SANITIZE else []), "-o", tmp, *_SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

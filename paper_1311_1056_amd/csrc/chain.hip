@@ -24,6 +24,7 @@
 // exp(X) = C(w) 1 + S(w) X with the even and odd series C, S in w.
 #include "chain.hpp"
 #include "philox.hpp"
+#include "reduce.hpp"
 #include "su3.hpp"
 
 #include <hip/hip_ext.h>
@@ -210,37 +211,12 @@ struct Chain {
 // the wavefront, then the chain's wavefronts in order), so that a chain's
 // result depends on n only; every thread of the chain gets the same value.
 
-// a double moved by a DPP lane permutation (CTRL: 0xB1 lanes 1 0 3 2 of each
-// quad, 0x4E lanes 2 3 0 1, 0x141 mirror within 8 lanes, 0x140 mirror within
-// 16): in registers, without the LDS crossbar that a shuffle goes through
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
-template <bool MAX>
-__device__ __forceinline__ double combine(double v, double o)
-{
-    return MAX ? fmax(v, o) : v + o;
-}
-
 template <bool MAX, int B>
 __device__ __forceinline__ double chain_all(double v, const Seg& g, ChainLds<B>& s)
 {
-    // a butterfly over the chain's lanes whose steps pair lanes by
-    // involutions (xor 32 and 16 by shuffle, then the 16- and 8-lane mirrors
-    // and the two quad swaps by DPP), so every lane adds the same pairs in
-    // the same order and ends with the same bits
-    if (g.T > 32) v = combine<MAX>(v, __shfl_xor(v, 32, 64));
-    if (g.T > 16) v = combine<MAX>(v, __shfl_xor(v, 16, 64));
-    if (g.T > 8) v = combine<MAX>(v, dpp_move<0x140>(v));
-    if (g.T > 4) v = combine<MAX>(v, dpp_move<0x141>(v));
-    if (g.T > 2) v = combine<MAX>(v, dpp_move<0x4E>(v));
-    if (g.T > 1) v = combine<MAX>(v, dpp_move<0xB1>(v));
+    // the butterfly of reduce.hpp over the chain's lanes: every lane adds the
+    // same pairs in the same order and ends with the same bits
+    v = group_reduce<MAX>(v, g.T);
     if (B > 64 && g.T > 64) {
         if ((g.t & 63) == 0) s.red[g.t >> 6] = v;
         __syncthreads();

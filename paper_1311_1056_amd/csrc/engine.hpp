@@ -57,6 +57,15 @@ hipError_t launch_zero(double* p, int n, hipStream_t st);
 constexpr int kMaxCoolBlocks = 512;
 __host__ __device__ inline int cool_chunks_total(int V) { return (2 * V + kBlock - 1) / kBlock; }
 
+// the chunks [c0, c1) of logical block lb when nch chunks of kBlock lanes are
+// spread over nblk blocks in contiguous runs (empty for blocks past the end)
+__host__ __device__ inline void chunk_range(int nch, int nblk, int lb, int& c0, int& c1)
+{
+    const int per = (nch + nblk - 1) / nblk;
+    c0 = lb * per;
+    c1 = (lb + 1) * per < nch ? (lb + 1) * per : nch;
+}
+
 // logical blocks a run of V sites needs per kind
 inline void blocks_per_kind(int V, int out[NKIND])
 {

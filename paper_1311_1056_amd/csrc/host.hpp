@@ -10,6 +10,7 @@
 
 #include "../../include/clgc.h"
 #include "engine.hpp"
+#include "sched.hpp"
 
 namespace clgc {
 
@@ -22,7 +23,6 @@ cl_status fail(cl_status st, const char* fmt, ...) __attribute__((format(printf,
         if (e_ != hipSuccess) return ::clgc::fail(CL_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // byte offsets of a lattice's pieces inside its device buffer
 struct Layout {

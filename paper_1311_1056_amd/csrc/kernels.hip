@@ -11,6 +11,7 @@
 // kernels of a step and no grid-wide fence is needed inside a sweep.
 #include "engine.hpp"
 #include "host.hpp"
+#include "reduce.hpp"
 
 #include <hip/hip_ext.h>
 #include <math.h>
@@ -23,50 +24,10 @@ namespace clgc {
 // ---------------------------------------------------------------------------
 // reductions
 
-// a value moved between lanes by a DPP permutation, in registers rather than
-// through the LDS crossbar: CTRL 0xB1 lanes 1 0 3 2 of each quad (l ^ 1),
-// 0x4E lanes 2 3 0 1 (l ^ 2), 0x141 the mirror within 8 lanes, 0x140 the
-// mirror within 16
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
+// Sum / max over the wavefront, the same bits in every lane (reduce.hpp).
+__device__ __forceinline__ double wave_sum(double v) { return group_reduce<false>(v, 64); }
 
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
-// Sum / max over the wavefront, the same bits in every lane: a butterfly whose
-// steps pair lanes by involutions (xor 32 and 16 by shuffle, then the 16- and
-// 8-lane mirrors and the two quad swaps by DPP), so each lane combines the
-// same pairs in the same order.
-__device__ __forceinline__ double wave_sum(double v)
-{
-    v += __shfl_xor(v, 32, 64);
-    v += __shfl_xor(v, 16, 64);
-    v += dpp_move<0x140>(v);
-    v += dpp_move<0x141>(v);
-    v += dpp_move<0x4E>(v);
-    v += dpp_move<0xB1>(v);
-    return v;
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-    v = fmax(v, __shfl_xor(v, 32, 64));
-    v = fmax(v, __shfl_xor(v, 16, 64));
-    v = fmax(v, dpp_move<0x140>(v));
-    v = fmax(v, dpp_move<0x141>(v));
-    v = fmax(v, dpp_move<0x4E>(v));
-    v = fmax(v, dpp_move<0xB1>(v));
-    return v;
-}
+__device__ __forceinline__ double wave_max(double v) { return group_reduce<true>(v, 64); }
 
 // Sum (or max) of NV values over the block; the result is valid in thread 0.
 // The order of operations is fixed, so the result depends on the inputs only.
@@ -161,13 +122,10 @@ __device__ __forceinline__ double wave_cool_sum(const RunArgs& ra) { return wave
 // ---------------------------------------------------------------------------
 // logical-block iteration
 
-// Workgroups are dispatched to the eight XCDs round-robin (workgroup w runs
-// on XCD w mod 8), and each XCD has its own L2.  Logical blocks are therefore
-// dealt out so that XCD x works through the contiguous range
-// [x Q, (x+1) Q) of the logical-block space: neighbouring sites, whose links
-// and clover matrices a block re-reads, stay in one L2.  Grids are launched as
-// a multiple of eight (or grid-stride with a multiple-of-eight stride), so the
-// XCD of a logical slot never changes.
+// Logical blocks are dealt to launch slots by logical_block (lattice.hpp), so
+// that each XCD works through a contiguous range of the lattice.  Grids are
+// launched as a multiple of eight (or grid-stride with a multiple-of-eight
+// stride), so the XCD of a logical slot never changes.
 // The body between CLGC_FOR_BLOCKS and CLGC_END_BLOCKS runs once per logical
 // block (ra, lb, tid); it is written once, as a lambda, and each kernel
 // instance inlines it into one of two loops: FAST, a single run whose RunArgs
@@ -185,7 +143,7 @@ __device__ __forceinline__ double wave_cool_sum(const RunArgs& ra) { return wave
         const int total_ = ka.one.nblk[kind_];                                 \
         const int q_ = (total_ + kXcds - 1) / kXcds;                           \
         for (int gb0_ = blockIdx.x; gb0_ < kXcds * q_; gb0_ += gridDim.x) {    \
-            const int gb_ = (gb0_ % kXcds) * q_ + gb0_ / kXcds;                \
+            const int gb_ = logical_block(gb0_, total_);                       \
             if (gb_ < total_) body_(ka.one, gb_);                              \
         }                                                                      \
     } else {                                                                   \
@@ -193,21 +151,13 @@ __device__ __forceinline__ double wave_cool_sum(const RunArgs& ra) { return wave
         const int total_ = hdr_->total[kind_];                                 \
         const int q_ = (total_ + kXcds - 1) / kXcds;                           \
         for (int gb0_ = blockIdx.x; gb0_ < kXcds * q_; gb0_ += gridDim.x) {    \
-            const int gb_ = (gb0_ % kXcds) * q_ + gb0_ / kXcds;                \
+            const int gb_ = logical_block(gb0_, total_);                       \
             if (gb_ >= total_) continue;                                       \
             const int run_ = find_run(hdr_, kind_, gb_);                       \
             body_(ka.runs[run_], gb_ - hdr_->begin[kind_][run_]);              \
         }                                                                      \
     }
 
-// decompose a link index l in [0, 4V): l = (mu * 2 + p) * Vh + h
-__device__ __forceinline__ void link_decompose(const RunArgs& ra, int l, int& mu, int& p, int& h)
-{
-    mu = l / ra.V;
-    const int rem = l - mu * ra.V;
-    p = rem >= ra.Vh;
-    h = rem - p * ra.Vh;
-}
 
 template <typename T>
 __device__ __forceinline__ mat3<T> ldU(const RunArgs& ra, int mu, const Site& s)
@@ -322,23 +272,6 @@ __global__ void __launch_bounds__(kBlock) k_pack(const KArgs ka,
         }
     }
     CLGC_END_BLOCKS
-}
-
-// Order of the regions (256 consecutive half-indices) inside one XCD's share
-// of a kernel that deals whole regions to XCDs: x3 fastest.  In half-index
-// order a region's x3 neighbours come a whole x3 slice of regions later, long
-// after its data left the XCD's L2; with the share transposed they run next
-// to it.  A bijection on the share; the identity when the share is not a
-// whole number of x3 slices.
-__device__ __forceinline__ int xcd_region_order(const RunArgs& ra, int region, int nreg)
-{
-    const int per = nreg / kXcds;
-    const int slice_h = ra.Vh / ra.L[3];
-    if (nreg % kXcds || slice_h % kBlock) return region;
-    const int slice = slice_h / kBlock;
-    if (slice == 0 || per % slice || per / slice < 2) return region;
-    const int c3 = per / slice, k = region % per;
-    return region - k + (k % c3) * slice + k / c3;
 }
 
 // ---------------------------------------------------------------------------
@@ -659,9 +592,10 @@ __global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
             __hip_atomic_store(&cr->kslot[par ^ 1][x][0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     const int nch = (4 * ra.V + kBlock - 1) / kBlock;
-    const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
+    int cb0, cb1;
+    chunk_range(nch, ra.nblk[KIND_COOL], lb, cb0, cb1);
     double un = 0.0;
-    for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+    for (int c = cb0; c < cb1; ++c) {
         const int t = c * kBlock + (int)threadIdx.x;
         if (t < 4 * ra.V && ok) {
             int mu, p, h;
@@ -1038,17 +972,19 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
-        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
-        for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+        int cb0, cb1;
+        chunk_range(nch, ra.nblk[KIND_COOL], lb, cb0, cb1);
+        for (int c = cb0; c < cb1; ++c) {
             const int t = c * kBlock + (int)threadIdx.x;
             const int h = t >> 2, mu = t & 3;
             const bool lane_ok = h < ra.Vh;
             herm3<double> G = h_zero<double>();
             if (lane_ok) {
-                const Site x = site_coords(ra, 0, h);
+                int of, ob;
+                cool_lane_links(ra, 0, h, mu, of, ob);
                 const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-                h_add_uudag(G, m_to_double(load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V)));
-                h_sub_udagu(G, m_to_double(load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V)));
+                h_add_uudag(G, m_to_double(load_mat(Uc, of, 4 * ra.V)));
+                h_sub_udagu(G, m_to_double(load_mat(Uc, ob, 4 * ra.V)));
             }
             // Each wavefront reads the status for itself (there is no barrier
             // here).  Within this launch the word changes only below, in block
@@ -1099,12 +1035,13 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
-        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
+        int cb0, cb1;
+        chunk_range(nch, ra.nblk[KIND_COOL], lb, cb0, cb1);
         // (no kernel writes the status during this launch: every wavefront
         // reads the same value, so the block reduction below is reached by all)
         bool ok = true;
         double un = 0.0;
-        for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+        for (int c = cb0; c < cb1; ++c) {
             const int t = c * kBlock + (int)threadIdx.x;
             const int h = t >> 2, mu = t & 3;
             const bool lane_ok = h < ra.Vh;
@@ -1114,8 +1051,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
             if (lane_ok) {
                 const Site y = site_coords(ra, 1, h);
                 const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
-                of = (mu * 2 + 1) * ra.Vh + h;
-                ob = link_off(ra, mu, yb);
+                cool_lane_links(ra, 1, h, mu, of, ob);
                 const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
                 const __amdgpu_buffer_rsrc_t om = omega_rsrc(ra);
                 Uf = mul_h(m_to_double(load_mat(Uc, of, 4 * ra.V)), load_herm<double>(om, site_half(ra, yf), ra.Vh, 9));
@@ -1162,10 +1098,11 @@ __device__ __forceinline__ void omega_loads(const RunArgs& ra, int c, int& h, bo
     h = t >> 2;
     lok = h < ra.Vh;
     if (lok) {
-        const Site x = site_coords(ra, 0, h);
+        int of, ob;
+        cool_lane_links(ra, 0, h, mu, of, ob);
         const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-        Af = load_mat(Uc, (mu * 2) * ra.Vh + h, 4 * ra.V);
-        Ab = load_mat(Uc, link_off(ra, mu, site_move(ra, x, mu, -1)), 4 * ra.V);
+        Af = load_mat(Uc, of, 4 * ra.V);
+        Ab = load_mat(Uc, ob, 4 * ra.V);
     }
 }
 
@@ -1176,8 +1113,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
-        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
-        const int c0 = lb * per, c1 = min((lb + 1) * per, nch);
+        int c0, c1;
+        chunk_range(nch, ra.nblk[KIND_COOL], lb, c0, c1);
         const int mu = (int)threadIdx.x & 3;
         int h = 0;
         bool lok = false;
@@ -1246,8 +1183,7 @@ __device__ __forceinline__ void apply_loads(const RunArgs& ra, int c, ApplyIn<T>
     if (in.lok) {
         const Site y = site_coords(ra, 1, h);
         const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
-        in.of = (mu * 2 + 1) * ra.Vh + h;
-        in.ob = link_off(ra, mu, yb);
+        cool_lane_links(ra, 1, h, mu, in.of, in.ob);
         const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
         const __amdgpu_buffer_rsrc_t om = omega_rsrc(ra);
         in.Uf = load_mat(Uc, in.of, 4 * ra.V);
@@ -1265,8 +1201,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int it
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
-        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
-        const int c0 = lb * per, c1 = min((lb + 1) * per, nch);
+        int c0, c1;
+        chunk_range(nch, ra.nblk[KIND_COOL], lb, c0, c1);
         ApplyIn<T> cur;
         cur.lok = false;
         if (c0 < c1) apply_loads(ra, c0, cur);
@@ -1320,9 +1256,10 @@ __global__ void __launch_bounds__(kBlock) k_gradnorm(const KArgs ka, int iter)
     Ctrl* cr = ra.ctrl;
     if (ra.mode == 2 && iter < ra.n_cool && cr->status == ST_OK) {
         const int nch = (2 * ra.V + kBlock - 1) / kBlock;
-        const int per = (nch + ra.nblk[KIND_COOL] - 1) / ra.nblk[KIND_COOL];
+        int cb0, cb1;
+        chunk_range(nch, ra.nblk[KIND_COOL], lb, cb0, cb1);
         double fs = 0.0;
-        for (int c = lb * per; c < (lb + 1) * per && c < nch; ++c) {
+        for (int c = cb0; c < cb1; ++c) {
             const int t = c * kBlock + (int)threadIdx.x;
             const int sx = t >> 1, half = t & 1;
             herm3<T> G = h_zero<T>();

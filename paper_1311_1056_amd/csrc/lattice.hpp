@@ -121,12 +121,12 @@ struct Site {
     int x0, x1, x2, x3;
 };
 
-__device__ __forceinline__ int site_get(const Site& s, int mu)
+__host__ __device__ __forceinline__ int site_get(const Site& s, int mu)
 {
     return mu == 0 ? s.x0 : (mu == 1 ? s.x1 : (mu == 2 ? s.x2 : s.x3));
 }
 
-__device__ __forceinline__ Site site_coords(const RunArgs& ra, int p, int h)
+__host__ __device__ __forceinline__ Site site_coords(const RunArgs& ra, int p, int h)
 {
     Site s;
     int r = h / ra.Lh0;
@@ -141,22 +141,22 @@ __device__ __forceinline__ Site site_coords(const RunArgs& ra, int p, int h)
     return s;
 }
 
-__device__ __forceinline__ int site_half(const RunArgs& ra, const Site& s)
+__host__ __device__ __forceinline__ int site_half(const RunArgs& ra, const Site& s)
 {
     return (s.x0 >> 1) + ra.Lh0 * (s.x1 + ra.L[1] * (s.x2 + ra.L[2] * s.x3));
 }
 
-__device__ __forceinline__ int site_parity(const Site& s) { return (s.x0 + s.x1 + s.x2 + s.x3) & 1; }
+__host__ __device__ __forceinline__ int site_parity(const Site& s) { return (s.x0 + s.x1 + s.x2 + s.x3) & 1; }
 
-__device__ __forceinline__ int site_lex(const RunArgs& ra, const Site& s)
+__host__ __device__ __forceinline__ int site_lex(const RunArgs& ra, const Site& s)
 {
     return s.x0 + ra.L[0] * (s.x1 + ra.L[1] * (s.x2 + ra.L[2] * s.x3));
 }
 
-__device__ __forceinline__ int wrap(int v, int L) { return v >= L ? v - L : (v < 0 ? v + L : v); }
+__host__ __device__ __forceinline__ int wrap(int v, int L) { return v >= L ? v - L : (v < 0 ? v + L : v); }
 
 // s + d * mu_hat with periodic wrap, d = +-1
-__device__ __forceinline__ Site site_move(const RunArgs& ra, const Site& s, int mu, int d)
+__host__ __device__ __forceinline__ Site site_move(const RunArgs& ra, const Site& s, int mu, int d)
 {
     Site r;
     r.x0 = mu == 0 ? wrap(s.x0 + d, ra.L[0]) : s.x0;
@@ -167,9 +167,59 @@ __device__ __forceinline__ Site site_move(const RunArgs& ra, const Site& s, int 
 }
 
 // offset (in complex elements, without the e * 4V term) of link (mu, site)
-__device__ __forceinline__ int link_off(const RunArgs& ra, int mu, const Site& s)
+__host__ __device__ __forceinline__ int link_off(const RunArgs& ra, int mu, const Site& s)
 {
     return (mu * 2 + site_parity(s)) * ra.Vh + site_half(ra, s);
+}
+
+// Logical block of a launch slot.  Workgroups are dispatched to the eight
+// XCDs round-robin (slot w runs on XCD w mod 8) and each XCD has its own L2:
+// slot w takes logical block (w mod 8) q + w / 8, q = ceil(total / 8), so XCD
+// x works through the contiguous range [x q, (x + 1) q) of the logical-block
+// space, where neighbouring sites re-read each other's links.  Slots whose
+// block is >= total have no work.  A bijection of [0, 8q) onto itself.
+__host__ __device__ __forceinline__ int logical_block(int slot, int total)
+{
+    const int q = (total + kXcds - 1) / kXcds;
+    return (slot % kXcds) * q + slot / kXcds;
+}
+
+// decompose a link index l in [0, 4V): l = (mu * 2 + p) * Vh + h
+__host__ __device__ __forceinline__ void link_decompose(const RunArgs& ra, int l, int& mu, int& p, int& h)
+{
+    mu = l / ra.V;
+    const int rem = l - mu * ra.V;
+    p = rem >= ra.Vh;
+    h = rem - p * ra.Vh;
+}
+
+// Order of the regions (256 consecutive half-indices) inside one XCD's share
+// of a kernel that deals whole regions to XCDs: x3 fastest.  In half-index
+// order a region's x3 neighbours come a whole x3 slice of regions later, long
+// after its data left the XCD's L2; with the share transposed they run next
+// to it.  A bijection on the share; the identity when the share is not a
+// whole number of x3 slices.
+__host__ __device__ __forceinline__ int xcd_region_order(const RunArgs& ra, int region, int nreg)
+{
+    const int per = nreg / kXcds;
+    const int slice_h = ra.Vh / ra.L[3];
+    if (nreg % kXcds || slice_h % kBlock) return region;
+    const int slice = slice_h / kBlock;
+    if (slice == 0 || per % slice || per / slice < 2) return region;
+    const int c3 = per / slice, k = region % per;
+    return region - k + (k % c3) * slice + k / c3;
+}
+
+// Cooling lanes.  Lane t of the 2V lanes of a cooling step (4 per site of one
+// parity, t = 4 h + mu) owns, at the site of parity p and half-index h, the
+// links U_mu(x) and U_mu(x - mu): each link has exactly one end of each
+// parity, so over all h and mu these are every link exactly once.  of / ob:
+// their offsets (complex elements, without the element stride).
+__host__ __device__ __forceinline__ void cool_lane_links(const RunArgs& ra, int p, int h, int mu, int& of, int& ob)
+{
+    const Site x = site_coords(ra, p, h);
+    of = (mu * 2 + p) * ra.Vh + h;
+    ob = link_off(ra, mu, site_move(ra, x, mu, -1));
 }
 
 // Field access through raw buffer instructions.  The field pointers come

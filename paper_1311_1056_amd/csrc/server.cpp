@@ -48,67 +48,6 @@ struct Kept {
     std::vector<double> links;
 };
 
-// first-fit allocator over [0, size) with coalescing of free ranges
-class Heap {
-public:
-    void reset(size_t size)
-    {
-        free_.clear();
-        if (size) free_[0] = size;
-        size_ = size;
-        used_ = 0;
-    }
-    bool alloc(size_t n, size_t* off)
-    {
-        n = align256(n);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                *off = it->first;
-                const size_t rest = it->second - n, start = it->first + n;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                used_ += n;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t n)
-    {
-        n = align256(n);
-        used_ -= n;
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t size() const { return size_; }
-    size_t used() const { return used_; }
-
-private:
-    std::map<size_t, size_t> free_;
-    size_t size_ = 0, used_ = 0;
-};
-
-double percentile(std::vector<float> v, double q)
-{
-    if (v.empty()) return 0.0;
-    std::sort(v.begin(), v.end());
-    const double pos = q * (double)(v.size() - 1);
-    const size_t i = (size_t)pos;
-    const double f = pos - (double)i;
-    return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
-}
-
 }  // namespace
 
 struct cl_server {
@@ -185,9 +124,9 @@ cl_status admit(cl_server* s)
 {
     while (!s->pending.empty()) {
         Run& r = *s->pending.front();
-        if ((int)s->group[r.desc.lattice.precision].size() >= kMaxRuns) break;
         size_t off = 0;
-        if (!s->heap.alloc(r.bytes, &off)) break;  // FIFO: wait for memory to free up
+        // FIFO: the head waits for a batch slot and memory to free up
+        if (!admit_head(s->heap, r.bytes, (int)s->group[r.desc.lattice.precision].size(), kMaxRuns, &off)) break;
         r.off = off;
         cl_status st = cl_lattice_create(&r.desc.lattice, s->arena + s->heap_base + off, r.bytes, s->stream, &r.lat);
         if (st == CL_OK) st = cl_lattice_init(r.lat, 1, r.desc.sigma_x, r.desc.sigma_y);

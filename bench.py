@@ -77,14 +77,15 @@ def algorithmic_cost(kind, V, rs, theta):
     L = 4 * V
     mat = 18 * rs
     prod, adj, hprod, hexp = 216, 126, 162, 500
+    om = (V // 2) * 18 * 8  # the even sites' Omega pairs, FP64 in both precisions
     if kind == "cool_omega":
         # read every link once, write Omega and Omega^-1 (18 reals) per even site;
         # per even site: 8 U U^dagger-type Hermitian products (54 flops) + one pair
-        return {"bytes": L * mat + (V // 2) * 18 * rs, "flops": (V // 2) * (8 * 54 + hexp)}
+        return {"bytes": L * mat + om, "flops": (V // 2) * (8 * 54 + hexp)}
     if kind == "cool_apply":
         # read and write every link once, read Omega pairs; per link: even transform,
         # odd transform (Hermitian products), per odd site: G and one exponential pair
-        return {"bytes": L * 2 * mat + (V // 2) * 18 * rs,
+        return {"bytes": L * 2 * mat + om,
                 "flops": L * 2 * hprod + (V // 2) * (8 * 54 + hexp)}
     if kind == "cool_step":
         # one cooling step in one kernel: every link read and written once (the

@@ -678,10 +678,11 @@ __device__ __forceinline__ T quad_sum(T v)
 
 // real Horner series for exp of a Hermitian traceless matrix (the Hermitian
 // counterpart of ch_exp_coeffs: s, t and the coefficients are real), N terms
+// (f0m1 = f0 - 1 without the cancellation: the last step's t z)
 template <typename T, int N>
-__device__ __forceinline__ void ch_exp_coeffs_real(T s, T t, T& f0, T& f1, T& f2)
+__device__ __forceinline__ void ch_exp_coeffs_real(T s, T t, T& f0, T& f1, T& f2, T& f0m1)
 {
-    T x = T(1), y = T(0), z = T(0);
+    T x = T(1), y = T(0), z = T(0), last = T(0);
 #pragma unroll
     for (int n = N; n >= 1; --n) {
         const T inv = T(1) / T(n);
@@ -691,10 +692,12 @@ __device__ __forceinline__ void ch_exp_coeffs_real(T s, T t, T& f0, T& f1, T& f2
         x = fma(inv, nx, T(1));
         y = inv * ny;
         z = inv * nz;
+        last = nx;
     }
     f0 = x;
     f1 = y;
     f2 = z;
+    f0m1 = last;
 }
 
 // square of a Hermitian matrix (Hermitian again)
@@ -726,8 +729,26 @@ __device__ __forceinline__ herm3<T> h_poly(T c0, T c1, T c2, const herm3<T>& A, 
     return R;
 }
 
-// E = exp(A), Ei = exp(-A) for Hermitian traceless A, both kept Hermitian
+// 2 D + D^2: (1 + D)^2 - 1
 template <typename T>
+__device__ __forceinline__ herm3<T> h_double_plus_square(const herm3<T>& D)
+{
+    const herm3<T> Q = h_square(D);
+    herm3<T> R;
+    R.d0 = fma(T(2), D.d0, Q.d0);
+    R.d1 = fma(T(2), D.d1, Q.d1);
+    R.d2 = fma(T(2), D.d2, Q.d2);
+    R.u01 = {fma(T(2), D.u01.re, Q.u01.re), fma(T(2), D.u01.im, Q.u01.im)};
+    R.u02 = {fma(T(2), D.u02.re, Q.u02.re), fma(T(2), D.u02.im, Q.u02.im)};
+    R.u12 = {fma(T(2), D.u12.re, Q.u12.re), fma(T(2), D.u12.im, Q.u12.im)};
+    return R;
+}
+
+// E = exp(A), Ei = exp(-A) for Hermitian traceless A, both kept Hermitian.
+// DELTA: E - 1 and Ei - 1 instead, formed without cancellation (the series'
+// constant term minus one, then (1 + D)^2 = 1 + 2 D + D^2 for each squaring),
+// which FP32 can store with all its digits when A is small
+template <typename T, bool DELTA = false>
 __device__ __forceinline__ void herm_exp_pair(herm3<T> A, herm3<T>& E, herm3<T>& Ei)
 {
     const T fro2 = A.d0 * A.d0 + A.d1 * A.d1 + A.d2 * A.d2 +
@@ -752,30 +773,40 @@ __device__ __forceinline__ void herm_exp_pair(herm3<T> A, herm3<T>& E, herm3<T>&
     const cx<T> w = A.u01 * A.u12 * conj(A.u02);
     const T t = A.d0 * A.d1 * A.d2 + T(2) * w.re - A.d0 * norm2(A.u12) - A.d1 * norm2(A.u02) -
                 A.d2 * norm2(A.u01);
-    T f0, f1, f2, g0, g1, g2;
+    T f0, f1, f2, g0, g1, g2, f0m1, g0m1;
     // The series needs exp_terms terms for |A|_F <= 1; a cooling step's A is
     // usually far smaller, and for |A|_F <= 1/8 the terms after the first 10
     // (FP64; 6 in FP32) add at most 3e-18 (1e-10) relative.  The choice is
     // taken per wavefront, so the loop stays uniform.
     constexpr int kShort = sizeof(T) == 8 ? 10 : 6;
     if (__all(fro2 * ldexp(T(1), -2 * k) <= T(1.0 / 64.0))) {
-        ch_exp_coeffs_real<T, kShort>(s, t, f0, f1, f2);
-        ch_exp_coeffs_real<T, kShort>(s, -t, g0, g1, g2);
+        ch_exp_coeffs_real<T, kShort>(s, t, f0, f1, f2, f0m1);
+        ch_exp_coeffs_real<T, kShort>(s, -t, g0, g1, g2, g0m1);
     } else {
-        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, t, f0, f1, f2);
-        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, -t, g0, g1, g2);
+        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, t, f0, f1, f2, f0m1);
+        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, -t, g0, g1, g2, g0m1);
     }
-    E = h_poly(f0, f1, f2, A, A2);
-    Ei = h_poly(g0, -g1, g2, A, A2);
-    for (int i = 0; i < k; ++i) {
-        E = h_square(E);
-        Ei = h_square(Ei);
+    if constexpr (DELTA) {
+        E = h_poly(f0m1, f1, f2, A, A2);
+        Ei = h_poly(g0m1, -g1, g2, A, A2);
+        for (int i = 0; i < k; ++i) {
+            E = h_double_plus_square(E);
+            Ei = h_double_plus_square(Ei);
+        }
+    } else {
+        E = h_poly(f0, f1, f2, A, A2);
+        Ei = h_poly(g0, -g1, g2, A, A2);
+        for (int i = 0; i < k; ++i) {
+            E = h_square(E);
+            Ei = h_square(Ei);
+        }
     }
 }
-// exp(A) alone, with the same operations herm_exp_pair applies to A: for -A
-// it reproduces that function's exp(-A) bit for bit (A^2 and the scaling do
-// not see the sign, det flips it, and c1 (-a) equals (-c1) a)
-template <typename T>
+// exp(A) alone (DELTA: exp(A) - 1), with the same operations herm_exp_pair
+// applies to A: for -A it reproduces that function's exp(-A) bit for bit (A^2
+// and the scaling do not see the sign, det flips it, and c1 (-a) equals
+// (-c1) a)
+template <typename T, bool DELTA = false>
 __device__ __forceinline__ void herm_exp_one(herm3<T> A, herm3<T>& E)
 {
     const T fro2 = A.d0 * A.d0 + A.d1 * A.d1 + A.d2 * A.d2 +
@@ -800,18 +831,23 @@ __device__ __forceinline__ void herm_exp_one(herm3<T> A, herm3<T>& E)
     const cx<T> w = A.u01 * A.u12 * conj(A.u02);
     const T t = A.d0 * A.d1 * A.d2 + T(2) * w.re - A.d0 * norm2(A.u12) - A.d1 * norm2(A.u02) -
                 A.d2 * norm2(A.u01);
-    T f0, f1, f2;
+    T f0, f1, f2, f0m1;
     // The series needs exp_terms terms for |A|_F <= 1; a cooling step's A is
     // usually far smaller, and for |A|_F <= 1/8 the terms after the first 10
     // (FP64; 6 in FP32) add at most 3e-18 (1e-10) relative.  The choice is
     // taken per wavefront, so the loop stays uniform.
     constexpr int kShort = sizeof(T) == 8 ? 10 : 6;
     if (__all(fro2 * ldexp(T(1), -2 * k) <= T(1.0 / 64.0)))
-        ch_exp_coeffs_real<T, kShort>(s, t, f0, f1, f2);
+        ch_exp_coeffs_real<T, kShort>(s, t, f0, f1, f2, f0m1);
     else
-        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, t, f0, f1, f2);
-    E = h_poly(f0, f1, f2, A, A2);
-    for (int i = 0; i < k; ++i) E = h_square(E);
+        ch_exp_coeffs_real<T, exp_terms<T>::n>(s, t, f0, f1, f2, f0m1);
+    if constexpr (DELTA) {
+        E = h_poly(f0m1, f1, f2, A, A2);
+        for (int i = 0; i < k; ++i) E = h_double_plus_square(E);
+    } else {
+        E = h_poly(f0, f1, f2, A, A2);
+        for (int i = 0; i < k; ++i) E = h_square(E);
+    }
 }
 
 // H U for Hermitian H
@@ -857,12 +893,66 @@ __device__ __forceinline__ mat3<T> mul_h(const mat3<T>& U, const herm3<T>& H)
 // link is read and written once per cooling step, and each product is the one
 // the separate half-sweeps would evaluate, in the same order.
 
-// the 18 reals of (Omega, Omega^-1) of even site h: value j at OM[j * Vh + h],
-// FP64 in both precisions (the drift buffer holds 72 V reals of the link
-// type, at least the 9 V doubles this needs)
+// How the cooling transforms are staged and applied.  FP64 stages Omega and
+// Omega^-1 themselves.  FP32 (mixed precision) stages Omega - 1 and
+// Omega^-1 - 1, whose entries are of the order of eps alpha G, so FP32 keeps
+// all their digits, and applies U + (Omega - 1) U: the product is rounded at
+// its own small scale and the sum once at the link's, where a product with
+// Omega itself (diagonal entries near 1) rounds at the link's scale in every
+// term.
+template <typename T>
+constexpr bool kCoolDelta = sizeof(T) == 4;
+
+// The even half-sweep on an odd site's lane, Uf Omega^-1 (the even site at
+// the link's end) and Omega Ub (the even site at its start).  FP64 transforms
+// Uf and Ub in place.  FP32 keeps the entering links and returns the small
+// corrections Tf = Uf (Omega^-1 - 1), Tb = (Omega - 1) Ub: the transformed
+// links are Uf + Tf and Ub + Tb (half_swept), and odd_transforms rounds the
+// cooling step's result once at the scale of the link.
+template <typename T>
+__device__ __forceinline__ void even_transforms(mat3<T>& Uf, mat3<T>& Ub, const herm3<T>& Rf, const herm3<T>& Lb,
+                                                mat3<T>& Tf, mat3<T>& Tb)
+{
+    if constexpr (kCoolDelta<T>) {
+        Tf = mul_h(Uf, Rf);
+        Tb = h_mul(Lb, Ub);
+    } else {
+        Uf = mul_h(Uf, Rf);
+        Ub = h_mul(Lb, Ub);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ mat3<T> half_swept(const mat3<T>& U, const mat3<T>& Tc)
+{
+    if constexpr (kCoolDelta<T>) return U + Tc;
+    else return U;
+}
+
+// The odd half-sweep: Nf = Omega_y (Uf Omega^-1), Nb = (Omega Ub) Omega_y^-1
+// with the staged (E, Ei) of the odd site.  FP32: Nf = Uf + (Tf + (Omega_y -
+// 1) (Uf + Tf)), every term but the last sum at its own small scale (and
+// likewise Nb).
+template <typename T>
+__device__ __forceinline__ void odd_transforms(const mat3<T>& Uf, const mat3<T>& Ub, const mat3<T>& Tf,
+                                               const mat3<T>& Tb, const herm3<T>& E, const herm3<T>& Ei, mat3<T>& Nf,
+                                               mat3<T>& Nb)
+{
+    if constexpr (kCoolDelta<T>) {
+        Nf = Uf + (Tf + h_mul(E, Uf + Tf));
+        Nb = Ub + (Tb + mul_h(Ub + Tb, Ei));
+    } else {
+        Nf = h_mul(E, Uf);
+        Nb = mul_h(Ub, Ei);
+    }
+}
+
+// the 18 reals of the staged (Omega, Omega^-1) of even site h: value j at
+// OM[j * Vh + h], in the link type
+template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t omega_rsrc(const RunArgs& ra)
 {
-    const uint32_t bytes = 18u * (uint32_t)ra.Vh * (uint32_t)sizeof(double);
+    const uint32_t bytes = 18u * (uint32_t)ra.Vh * (uint32_t)sizeof(T);
     return __builtin_amdgcn_make_buffer_rsrc(ra.K, (short)0, (int)bytes, kBufferWord3);
 }
 
@@ -921,7 +1011,8 @@ __device__ __forceinline__ void store_herm(__amdgpu_buffer_rsrc_t rs, int h, int
     buf_store_scalar<T>(rs, lane, 8 * es, H.u12.im);
 }
 
-// quad-reduced G (each lane holds its mu share) -> Omega = exp(coef TL(G)) and its inverse
+// quad-reduced G (each lane holds its mu share) -> Omega = exp(coef TL(G)) and
+// its inverse, as the cooling kernels stage them (kCoolDelta)
 template <typename T>
 __device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm3<T>& Ei)
 {
@@ -939,7 +1030,7 @@ __device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm
     A.u01 = coef * G.u01;
     A.u02 = coef * G.u02;
     A.u12 = coef * G.u12;
-    herm_exp_pair(A, E, Ei);
+    herm_exp_pair<T, kCoolDelta<T>>(A, E, Ei);
 }
 // the same for one of the pair: coef < 0 gives Omega, coef > 0 Omega^-1
 template <typename T>
@@ -959,7 +1050,7 @@ __device__ __forceinline__ void site_omega_one(herm3<T> G, T coef, herm3<T>& E)
     A.u01 = coef * G.u01;
     A.u02 = coef * G.u02;
     A.u12 = coef * G.u12;
-    herm_exp_one(A, E);
+    herm_exp_one<T, kCoolDelta<T>>(A, E);
 }
 
 // In both kernels the link loads are issued first: the run's state (status,
@@ -978,13 +1069,13 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
             const int t = c * kBlock + (int)threadIdx.x;
             const int h = t >> 2, mu = t & 3;
             const bool lane_ok = h < ra.Vh;
-            herm3<double> G = h_zero<double>();
+            herm3<T> G = h_zero<T>();
             if (lane_ok) {
                 int of, ob;
                 cool_lane_links(ra, 0, h, mu, of, ob);
                 const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-                h_add_uudag(G, m_to_double(load_mat(Uc, of, 4 * ra.V)));
-                h_sub_udagu(G, m_to_double(load_mat(Uc, ob, 4 * ra.V)));
+                h_add_uudag(G, load_mat(Uc, of, 4 * ra.V));
+                h_sub_udagu(G, load_mat(Uc, ob, 4 * ra.V));
             }
             // Each wavefront reads the status for itself (there is no barrier
             // here).  Within this launch the word changes only below, in block
@@ -1018,10 +1109,10 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
             }
             // lane 0 of the quad forms Omega, lane 1 Omega^-1 (the others do
             // not store)
-            const double coef = -4.0 * ra.eps_c * alpha_ad;
-            herm3<double> E;
+            const T coef = T(-4.0 * ra.eps_c * alpha_ad);
+            herm3<T> E;
             site_omega_one(G, mu == 1 ? -coef : coef, E);
-            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
         }
     }
     CLGC_END_BLOCKS
@@ -1045,30 +1136,32 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
             const int t = c * kBlock + (int)threadIdx.x;
             const int h = t >> 2, mu = t & 3;
             const bool lane_ok = h < ra.Vh;
-            herm3<double> G = h_zero<double>();
-            mat3<double> Uf, Ub;
+            herm3<T> G = h_zero<T>();
+            mat3<T> Uf, Ub, Tf, Tb;
             int of = 0, ob = 0;
             if (lane_ok) {
                 const Site y = site_coords(ra, 1, h);
                 const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
                 cool_lane_links(ra, 1, h, mu, of, ob);
                 const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-                const __amdgpu_buffer_rsrc_t om = omega_rsrc(ra);
-                Uf = mul_h(m_to_double(load_mat(Uc, of, 4 * ra.V)), load_herm<double>(om, site_half(ra, yf), ra.Vh, 9));
-                Ub = h_mul(load_herm<double>(om, site_half(ra, yb), ra.Vh, 0), m_to_double(load_mat(Uc, ob, 4 * ra.V)));
-                h_add_uudag(G, Uf);
-                h_sub_udagu(G, Ub);
+                const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
+                Uf = load_mat(Uc, of, 4 * ra.V);
+                Ub = load_mat(Uc, ob, 4 * ra.V);
+                even_transforms(Uf, Ub, load_herm<T>(om, site_half(ra, yf), ra.Vh, 9),
+                                load_herm<T>(om, site_half(ra, yb), ra.Vh, 0), Tf, Tb);
+                h_add_uudag(G, half_swept(Uf, Tf));
+                h_sub_udagu(G, half_swept(Ub, Tb));
             }
             ok = cr->status == ST_OK;
-            herm3<double> E, Ei;
-            site_omega(G, -4.0 * ra.eps_c * cr->alpha_cur, E, Ei);
+            herm3<T> E, Ei;
+            site_omega(G, T(-4.0 * ra.eps_c * cr->alpha_cur), E, Ei);
             if (ok && lane_ok) {
-                const mat3<double> Nf = h_mul(E, Uf);
-                const mat3<double> Nb = mul_h(Ub, Ei);
+                mat3<T> Nf, Nb;
+                odd_transforms(Uf, Ub, Tf, Tb, E, Ei, Nf, Nb);
                 cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
-                store_mat(Uw, of, 4 * ra.V, m_cast_from<T>(Nf));
-                store_mat(Uw, ob, 4 * ra.V, m_cast_from<T>(Nb));
-                un += m_norm2(Nf) + m_norm2(Nb);
+                store_mat(Uw, of, 4 * ra.V, Nf);
+                store_mat(Uw, ob, 4 * ra.V, Nb);
+                un += (double)m_norm2(Nf) + (double)m_norm2(Nb);
             }
         }
         // every link is written exactly once: the sum is the unitarity norm of
@@ -1141,20 +1234,20 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
                 cr->hist_n = iter + 1;
             }
         }
-        const double coef = -4.0 * ra.eps_c * alpha_ad;
+        const T coef = T(-4.0 * ra.eps_c * alpha_ad);
         for (int c = c0; c < c1; ++c) {
             int hn = 0;
             bool lokn = false;
             mat3<T> Nf, Nb;
             if (c + 1 < c1) omega_loads(ra, c + 1, hn, lokn, Nf, Nb);
-            herm3<double> G = h_zero<double>();
+            herm3<T> G = h_zero<T>();
             if (lok) {
-                h_add_uudag(G, m_to_double(Af));
-                h_sub_udagu(G, m_to_double(Ab));
+                h_add_uudag(G, Af);
+                h_sub_udagu(G, Ab);
             }
-            herm3<double> E;
+            herm3<T> E;
             site_omega_one(G, mu == 1 ? -coef : coef, E);
-            if (ok && lok && mu < 2) store_herm(omega_rsrc(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            if (ok && lok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
             h = hn;
             lok = lokn;
             Af = Nf;
@@ -1169,7 +1262,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
 template <typename T>
 struct ApplyIn {
     mat3<T> Uf, Ub;
-    herm3<double> Eif, Eb;
+    herm3<T> Eif, Eb;
     int of, ob;
     bool lok;
 };
@@ -1185,10 +1278,10 @@ __device__ __forceinline__ void apply_loads(const RunArgs& ra, int c, ApplyIn<T>
         const Site yb = site_move(ra, y, mu, -1), yf = site_move(ra, y, mu, +1);
         cool_lane_links(ra, 1, h, mu, in.of, in.ob);
         const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
-        const __amdgpu_buffer_rsrc_t om = omega_rsrc(ra);
+        const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
         in.Uf = load_mat(Uc, in.of, 4 * ra.V);
-        in.Eif = load_herm<double>(om, site_half(ra, yf), ra.Vh, 9);
-        in.Eb = load_herm<double>(om, site_half(ra, yb), ra.Vh, 0);
+        in.Eif = load_herm<T>(om, site_half(ra, yf), ra.Vh, 9);
+        in.Eb = load_herm<T>(om, site_half(ra, yb), ra.Vh, 0);
         in.Ub = load_mat(Uc, in.ob, 4 * ra.V);
     }
 }
@@ -1208,29 +1301,28 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int it
         if (c0 < c1) apply_loads(ra, c0, cur);
         // (no kernel writes the status during this launch)
         const bool ok = cr->status == ST_OK;
-        const double coef = -4.0 * ra.eps_c * cr->alpha_cur;
+        const T coef = T(-4.0 * ra.eps_c * cr->alpha_cur);
         double un = 0.0;
         for (int c = c0; c < c1; ++c) {
             ApplyIn<T> nxt;
             nxt.lok = false;
             if (c + 1 < c1) apply_loads(ra, c + 1, nxt);
-            herm3<double> G = h_zero<double>();
-            mat3<double> Uf, Ub;
+            herm3<T> G = h_zero<T>();
+            mat3<T> Uf = cur.Uf, Ub = cur.Ub, Tf, Tb;
             if (cur.lok) {
-                Uf = mul_h(m_to_double(cur.Uf), cur.Eif);
-                Ub = h_mul(cur.Eb, m_to_double(cur.Ub));
-                h_add_uudag(G, Uf);
-                h_sub_udagu(G, Ub);
+                even_transforms(Uf, Ub, cur.Eif, cur.Eb, Tf, Tb);
+                h_add_uudag(G, half_swept(Uf, Tf));
+                h_sub_udagu(G, half_swept(Ub, Tb));
             }
-            herm3<double> E, Ei;
+            herm3<T> E, Ei;
             site_omega(G, coef, E, Ei);
             if (ok && cur.lok) {
-                const mat3<double> Nf = h_mul(E, Uf);
-                const mat3<double> Nb = mul_h(Ub, Ei);
+                mat3<T> Nf, Nb;
+                odd_transforms(Uf, Ub, Tf, Tb, E, Ei, Nf, Nb);
                 cx<T>* __restrict__ Uw = (cx<T>*)ra.U;
-                store_mat(Uw, cur.of, 4 * ra.V, m_cast_from<T>(Nf));
-                store_mat(Uw, cur.ob, 4 * ra.V, m_cast_from<T>(Nb));
-                un += m_norm2(Nf) + m_norm2(Nb);
+                store_mat(Uw, cur.of, 4 * ra.V, Nf);
+                store_mat(Uw, cur.ob, 4 * ra.V, Nb);
+                un += (double)m_norm2(Nf) + (double)m_norm2(Nb);
             }
             cur = nxt;
         }

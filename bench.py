@@ -77,7 +77,7 @@ def algorithmic_cost(kind, V, rs, theta):
     L = 4 * V
     mat = 18 * rs
     prod, adj, hprod, hexp = 216, 126, 162, 500
-    om = (V // 2) * 18 * 8  # the even sites' Omega pairs, FP64 in both precisions
+    om = (V // 2) * mat  # the even sites' staged Omega pairs, in the link type
     if kind == "cool_omega":
         # read every link once, write Omega and Omega^-1 (18 reals) per even site;
         # per even site: 8 U U^dagger-type Hermitian products (54 flops) + one pair

@@ -656,24 +656,16 @@ __global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
 // ---------------------------------------------------------------------------
 // gauge cooling half-sweep
 //
-// Four lanes per site x of the active parity, lane mu owning U_mu(x) and
-// U_mu(x - mu): every link has exactly one end of each parity, so the
-// half-sweep reads and writes every link exactly once.  The lanes add their
-// share of G_x = sum_mu (U_mu(x) U_mu(x)^dagger - U_mu(x-mu)^dagger U_mu(x-mu))
-// with two quad shuffles; sum_a f_ax lambda_a = 4 G_x (G_x is traceless
+// Four lanes per site x of the active parity (one per wavefront of a chunk of
+// 64 sites), lane mu owning U_mu(x) and U_mu(x - mu): every link has exactly
+// one end of each parity, so the half-sweep reads and writes every link
+// exactly once.  The four lanes' shares of G_x = sum_mu (U_mu(x)
+// U_mu(x)^dagger - U_mu(x-mu)^dagger U_mu(x-mu)) are added through LDS
+// (site_sum); sum_a f_ax lambda_a = 4 G_x (G_x is traceless
 // Hermitian), so Omega_x = exp(-4 eps alpha G_x), a Hermitian matrix whose
 // exponential has real Cayley-Hamilton coefficients; Omega_x^{-1} =
 // exp(+4 eps alpha G_x) uses the same series with det -> -det.
 
-// the sum over the quad, the same in its four lanes (each adds the same two
-// pairs in the same order)
-template <typename T>
-__device__ __forceinline__ T quad_sum(T v)
-{
-    v += dpp_move<0xB1>(v);
-    v += dpp_move<0x4E>(v);
-    return v;
-}
 
 
 // real Horner series for exp of a Hermitian traceless matrix (the Hermitian
@@ -1011,17 +1003,44 @@ __device__ __forceinline__ void store_herm(__amdgpu_buffer_rsrc_t rs, int h, int
     buf_store_scalar<T>(rs, lane, 8 * es, H.u12.im);
 }
 
-// quad-reduced G (each lane holds its mu share) -> Omega = exp(coef TL(G)) and
-// its inverse, as the cooling kernels stage them (kCoolDelta)
+// The four wavefronts of a cooling chunk hold the direction shares s_mu of
+// G at the chunk's 64 sites (wave mu, lane = site).  They exchange them
+// through LDS and every wavefront forms G = (s_0 + s_1) + (s_2 + s_3), the
+// same bits in all four.  Two buffers, used in turn: a buffer is written
+// again only two exchanges later, after every lane has passed the barrier of
+// the exchange in between, so one barrier per exchange suffices.
 template <typename T>
-__device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm3<T>& Ei)
+struct CoolShare {
+    T g[2][4][9][kCoolSites];
+};
+
+template <typename T>
+__device__ __forceinline__ herm3<T> site_sum(const herm3<T>& S, CoolShare<T>& sh, int& buf)
 {
-    G.d0 = quad_sum(G.d0);
-    G.d1 = quad_sum(G.d1);
-    G.d2 = quad_sum(G.d2);
-    G.u01 = {quad_sum(G.u01.re), quad_sum(G.u01.im)};
-    G.u02 = {quad_sum(G.u02.re), quad_sum(G.u02.im)};
-    G.u12 = {quad_sum(G.u12.re), quad_sum(G.u12.im)};
+    const int lane = (int)threadIdx.x & (kCoolSites - 1), mu = (int)threadIdx.x / kCoolSites;
+    T (*g)[9][kCoolSites] = sh.g[buf];
+    buf ^= 1;
+    const T v[9] = {S.d0, S.d1, S.d2, S.u01.re, S.u01.im, S.u02.re, S.u02.im, S.u12.re, S.u12.im};
+#pragma unroll
+    for (int j = 0; j < 9; ++j) g[mu][j][lane] = v[j];
+    __syncthreads();
+    T r[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) r[j] = (g[0][j][lane] + g[1][j][lane]) + (g[2][j][lane] + g[3][j][lane]);
+    herm3<T> G;
+    G.d0 = r[0];
+    G.d1 = r[1];
+    G.d2 = r[2];
+    G.u01 = {r[3], r[4]};
+    G.u02 = {r[5], r[6]};
+    G.u12 = {r[7], r[8]};
+    return G;
+}
+
+// coef TL(G) for the site sum G
+template <typename T>
+__device__ __forceinline__ herm3<T> scaled_traceless(const herm3<T>& G, T coef)
+{
     const T tr = (G.d0 + G.d1 + G.d2) * T(1.0 / 3.0);
     herm3<T> A;
     A.d0 = coef * (G.d0 - tr);
@@ -1030,27 +1049,21 @@ __device__ __forceinline__ void site_omega(herm3<T> G, T coef, herm3<T>& E, herm
     A.u01 = coef * G.u01;
     A.u02 = coef * G.u02;
     A.u12 = coef * G.u12;
-    herm_exp_pair<T, kCoolDelta<T>>(A, E, Ei);
+    return A;
+}
+
+// Omega = exp(coef TL(G)) and its inverse, as the cooling kernels stage them
+// (kCoolDelta)
+template <typename T>
+__device__ __forceinline__ void site_omega(const herm3<T>& G, T coef, herm3<T>& E, herm3<T>& Ei)
+{
+    herm_exp_pair<T, kCoolDelta<T>>(scaled_traceless(G, coef), E, Ei);
 }
 // the same for one of the pair: coef < 0 gives Omega, coef > 0 Omega^-1
 template <typename T>
-__device__ __forceinline__ void site_omega_one(herm3<T> G, T coef, herm3<T>& E)
+__device__ __forceinline__ void site_omega_one(const herm3<T>& G, T coef, herm3<T>& E)
 {
-    G.d0 = quad_sum(G.d0);
-    G.d1 = quad_sum(G.d1);
-    G.d2 = quad_sum(G.d2);
-    G.u01 = {quad_sum(G.u01.re), quad_sum(G.u01.im)};
-    G.u02 = {quad_sum(G.u02.re), quad_sum(G.u02.im)};
-    G.u12 = {quad_sum(G.u12.re), quad_sum(G.u12.im)};
-    const T tr = (G.d0 + G.d1 + G.d2) * T(1.0 / 3.0);
-    herm3<T> A;
-    A.d0 = coef * (G.d0 - tr);
-    A.d1 = coef * (G.d1 - tr);
-    A.d2 = coef * (G.d2 - tr);
-    A.u01 = coef * G.u01;
-    A.u02 = coef * G.u02;
-    A.u12 = coef * G.u12;
-    herm_exp_one<T, kCoolDelta<T>>(A, E);
+    herm_exp_one<T, kCoolDelta<T>>(scaled_traceless(G, coef), E);
 }
 
 // In both kernels the link loads are issued first: the run's state (status,
@@ -1059,6 +1072,8 @@ __device__ __forceinline__ void site_omega_one(herm3<T> G, T coef, herm3<T>& E)
 template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
 {
+    __shared__ CoolShare<T> sh;
+    int buf = 0;
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
@@ -1066,8 +1081,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
         int cb0, cb1;
         chunk_range(nch, ra.nblk[KIND_COOL], lb, cb0, cb1);
         for (int c = cb0; c < cb1; ++c) {
-            const int t = c * kBlock + (int)threadIdx.x;
-            const int h = t >> 2, mu = t & 3;
+            int h, mu;
+            cool_lane(c, (int)threadIdx.x, h, mu);
             const bool lane_ok = h < ra.Vh;
             herm3<T> G = h_zero<T>();
             if (lane_ok) {
@@ -1107,12 +1122,15 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
                     cr->hist_n = iter + 1;
                 }
             }
-            // lane 0 of the quad forms Omega, lane 1 Omega^-1 (the others do
-            // not store)
+            // wavefront 0 forms Omega, wavefront 1 Omega^-1 (2 and 3 only
+            // contribute their shares)
             const T coef = T(-4.0 * ra.eps_c * alpha_ad);
-            herm3<T> E;
-            site_omega_one(G, mu == 1 ? -coef : coef, E);
-            if (ok && lane_ok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            const herm3<T> Gx = site_sum(G, sh, buf);
+            if (mu < 2) {
+                herm3<T> E;
+                site_omega_one(Gx, mu == 1 ? -coef : coef, E);
+                if (ok && lane_ok) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            }
         }
     }
     CLGC_END_BLOCKS
@@ -1122,6 +1140,8 @@ template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
 {
     __shared__ double lds[8];
+    __shared__ CoolShare<T> sh;
+    int buf = 0;
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
@@ -1133,8 +1153,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
         bool ok = true;
         double un = 0.0;
         for (int c = cb0; c < cb1; ++c) {
-            const int t = c * kBlock + (int)threadIdx.x;
-            const int h = t >> 2, mu = t & 3;
+            int h, mu;
+            cool_lane(c, (int)threadIdx.x, h, mu);
             const bool lane_ok = h < ra.Vh;
             herm3<T> G = h_zero<T>();
             mat3<T> Uf, Ub, Tf, Tb;
@@ -1154,7 +1174,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
             }
             ok = cr->status == ST_OK;
             herm3<T> E, Ei;
-            site_omega(G, T(-4.0 * ra.eps_c * cr->alpha_cur), E, Ei);
+            site_omega(site_sum(G, sh, buf), T(-4.0 * ra.eps_c * cr->alpha_cur), E, Ei);
             if (ok && lane_ok) {
                 mat3<T> Nf, Nb;
                 odd_transforms(Uf, Ub, Tf, Tb, E, Ei, Nf, Nb);
@@ -1186,9 +1206,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
 template <typename T>
 __device__ __forceinline__ void omega_loads(const RunArgs& ra, int c, int& h, bool& lok, mat3<T>& Af, mat3<T>& Ab)
 {
-    const int t = c * kBlock + (int)threadIdx.x;
-    const int mu = t & 3;
-    h = t >> 2;
+    int mu;
+    cool_lane(c, (int)threadIdx.x, h, mu);
     lok = h < ra.Vh;
     if (lok) {
         int of, ob;
@@ -1202,13 +1221,15 @@ __device__ __forceinline__ void omega_loads(const RunArgs& ra, int c, int& h, bo
 template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int iter)
 {
+    __shared__ CoolShare<T> sh;
+    int buf = 0;
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
         int c0, c1;
         chunk_range(nch, ra.nblk[KIND_COOL], lb, c0, c1);
-        const int mu = (int)threadIdx.x & 3;
+        const int mu = (int)threadIdx.x / kCoolSites;
         int h = 0;
         bool lok = false;
         mat3<T> Af, Ab;
@@ -1245,9 +1266,12 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
                 h_add_uudag(G, Af);
                 h_sub_udagu(G, Ab);
             }
-            herm3<T> E;
-            site_omega_one(G, mu == 1 ? -coef : coef, E);
-            if (ok && lok && mu < 2) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            const herm3<T> Gx = site_sum(G, sh, buf);
+            if (mu < 2) {
+                herm3<T> E;
+                site_omega_one(Gx, mu == 1 ? -coef : coef, E);
+                if (ok && lok) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
+            }
             h = hn;
             lok = lokn;
             Af = Nf;
@@ -1270,8 +1294,8 @@ struct ApplyIn {
 template <typename T>
 __device__ __forceinline__ void apply_loads(const RunArgs& ra, int c, ApplyIn<T>& in)
 {
-    const int t = c * kBlock + (int)threadIdx.x;
-    const int h = t >> 2, mu = t & 3;
+    int h, mu;
+    cool_lane(c, (int)threadIdx.x, h, mu);
     in.lok = h < ra.Vh;
     if (in.lok) {
         const Site y = site_coords(ra, 1, h);
@@ -1290,6 +1314,8 @@ template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int iter)
 {
     __shared__ double lds[8];
+    __shared__ CoolShare<T> sh;
+    int buf = 0;
     CLGC_FOR_BLOCKS(KIND_COOL)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
@@ -1315,7 +1341,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int it
                 h_sub_udagu(G, half_swept(Ub, Tb));
             }
             herm3<T> E, Ei;
-            site_omega(G, coef, E, Ei);
+            site_omega(site_sum(G, sh, buf), coef, E, Ei);
             if (ok && cur.lok) {
                 mat3<T> Nf, Nb;
                 odd_transforms(Uf, Ub, Tf, Tb, E, Ei, Nf, Nb);

@@ -210,9 +210,24 @@ __host__ __device__ __forceinline__ int xcd_region_order(const RunArgs& ra, int 
     return region - k + (k % c3) * slice + k / c3;
 }
 
-// Cooling lanes.  Lane t of the 2V lanes of a cooling step (4 per site of one
-// parity, t = 4 h + mu) owns, at the site of parity p and half-index h, the
-// links U_mu(x) and U_mu(x - mu): each link has exactly one end of each
+// Cooling lanes.  A cooling step runs 4 lanes per site of one parity, in
+// chunks of kBlock lanes that cover kCoolSites consecutive half-indices: lane
+// t of chunk c takes the site h = kCoolSites c + (t mod kCoolSites) and the
+// direction mu = t / kCoolSites, so each wavefront handles one direction for
+// 64 consecutive sites and its load of a link element covers 64 neighbouring
+// entries of that direction's array (with one site per four lanes, a
+// wavefront's load is split over four arrays in pieces of 16 entries, which
+// streams measurably slower in FP32).
+constexpr int kCoolSites = kBlock / 4;
+static_assert(kCoolSites == 64, "one wavefront per direction");
+__host__ __device__ __forceinline__ void cool_lane(int c, int t, int& h, int& mu)
+{
+    h = c * kCoolSites + (t & (kCoolSites - 1));
+    mu = t / kCoolSites;
+}
+
+// The lane at the site of parity p and half-index h with direction mu owns
+// the links U_mu(x) and U_mu(x - mu): each link has exactly one end of each
 // parity, so over all h and mu these are every link exactly once.  of / ob:
 // their offsets (complex elements, without the element stride).
 __host__ __device__ __forceinline__ void cool_lane_links(const RunArgs& ra, int p, int h, int mu, int& of, int& ob)

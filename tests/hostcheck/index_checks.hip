@@ -60,7 +60,9 @@ static void check_cooling(const int* d)
             for (int c = c0; c < c1; ++c) {
                 chunk[c]++;
                 for (int lane = 0; lane < kBlock; ++lane) {
-                    const int t = c * kBlock + lane, h = t >> 2, mu = t & 3;
+                    int h, mu;
+                    cool_lane(c, lane, h, mu);
+                    if (mu < 0 || mu > 3 || h < c * kCoolSites || h >= (c + 1) * kCoolSites) ok = false;
                     if (h >= a.Vh) continue;
                     int of, ob;
                     cool_lane_links(a, p, h, mu, of, ob);

@@ -380,13 +380,86 @@ __device__ __forceinline__ cx<T> inv_det(const mat3<T>& M, const mat3<T>& Ma)
     return {d.re * r, -d.im * r};
 }
 
-// FP64 with the theta term runs one wave per SIMD: its walk needs ~440
-// registers, which then live in the VGPRs and AGPRs without touching scratch
-// (at two waves it spills hundreds of bytes per lane)
+// A lane's accumulator matrix kept in LDS: 18 values in a column of its own
+// (acc[j * kBlock + thread]), so no lane reads another's and no barrier is
+// needed.
+template <typename T>
+__device__ __forceinline__ void lds_acc_add(T* acc, const mat3<T>& m)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        T* c = acc + (2 * e) * kBlock + threadIdx.x;
+        c[0] += m.e[e / 3][e % 3].re;
+        c[kBlock] += m.e[e / 3][e % 3].im;
+    }
+}
+template <typename T>
+__device__ __forceinline__ mat3<T> lds_acc_get(const T* acc)
+{
+    mat3<T> m;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const T* c = acc + (2 * e) * kBlock + threadIdx.x;
+        m.e[e / 3][e % 3] = {c[0], c[kBlock]};
+    }
+    return m;
+}
+
+// One loop (nu, s = S) of the theta drift with the lane's A and B in LDS:
+// the loop's terms cb P + Q P + P X0 and -cb P' + P' Q + X0 P' are formed in
+// registers and added to the accumulators there.  The products are those of
+// the walk in k_drift, in the same order.
+template <typename T, int S>
+__device__ __forceinline__ void theta_loop_lds(const RunArgs& ra, const cx<T>* __restrict__ Ub,
+                                               const cx<T>* __restrict__ Fb, int fo, const Site& x,
+                                               const Site& d1, int mu, int nu, int p, int h, cx<T> cb, cx<T> mcb,
+                                               cx<T> cts, T* accA, T* accB)
+{
+    const int us = 4 * ra.V, fs = 6 * ra.V;
+    const Site d3 = site_move(ra, x, nu, S);
+    const Site d2 = site_move(ra, d1, nu, S);
+    const mat3<T> ub = load_mat(Ub, link_off(ra, mu, d3), us);
+    const mat3<T> X3 = load_mat(Fb, fo + link_off(ra, 0, d3), fs);
+    const mat3<T> e2 = m_adj(ub);
+    mat3<T> Y = (e2 * X3) * ub;
+    Y = m_scale(Y, inv_det(ub, e2)) + load_mat(Fb, fo + link_off(ra, 0, d2), fs);
+    __builtin_amdgcn_sched_barrier(0);
+    const mat3<T> ua = load_mat(Ub, link_off(ra, nu, S > 0 ? d1 : d2), us);
+    const mat3<T> ua_adj = m_adj(ua);
+    const cx<T> ida = inv_det(ua, ua_adj);
+    const mat3<T>& e1 = S > 0 ? ua : ua_adj;
+    const mat3<T>& e1i = S > 0 ? ua_adj : ua;
+    const mat3<T> R = e1 * e2;
+    mat3<T> Q = m_scale((e1 * Y) * e1i, ida) + load_mat(Fb, fo + link_off(ra, 0, d1), fs);
+    __builtin_amdgcn_sched_barrier(0);
+    mat3<T> e3 = load_mat(Ub, link_off(ra, nu, S > 0 ? x : d3), us);
+    if (S > 0) e3 = m_adj(e3);
+    const mat3<T> Pm = R * e3;
+    Q = m_scale(Q, cts);
+    const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
+    mat3<T> a = m_scale(Pm, cb);
+    m_mac(a, Q, Pm);
+    m_mac(a, Pm, X0s);
+    lds_acc_add(accA, a);
+    const mat3<T> Pa = m_adj(Pm);
+    mat3<T> b = m_scale(Pa, mcb);
+    m_mac(b, Pa, Q);
+    m_mac(b, X0s, Pa);
+    lds_acc_add(accB, b);
+}
+
+// FP64 with the theta term keeps each lane's A and B in LDS (36 doubles a
+// lane, 72 KB a block): the walk then fits in 256 registers and two waves
+// run per SIMD, where A and B in registers (about 440 with the walk) allow
+// one.  FP32 (two waves with them in registers, three in LDS, at the same
+// speed: it is bound by its arithmetic) and the Wilson-only drift keep them
+// in registers.
 template <typename T, bool THETA, bool FAST>
-__global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_drift(const KArgs ka)
+__global__ void __launch_bounds__(kBlock, 2) k_drift(const KArgs ka)
 {
     __shared__ double lds[8];
+    constexpr bool kAccLds = sizeof(T) == 8 && THETA;
+    __shared__ T accl[kAccLds ? 36 * kBlock : 1];
     CLGC_FOR_BLOCKS(KIND_DRIFT)
     // logical block -> (region of 256 half-indices, direction, parity): the eight
     // (mu, parity) blocks of a region are adjacent, so one XCD covers all the
@@ -409,31 +482,37 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
         const bool th = THETA && ra.has_theta;
         // A = sum (cb P + cts I),  B = sum (cts J - cb P'):  Khat = TL(e0 A + B e0')
         mat3<T> A = m_zero<T>(), B = m_zero<T>();
+        if (kAccLds && th) {
+            T* accA = accl;
+            T* accB = accl + 18 * kBlock;
+#pragma unroll
+            for (int j = 0; j < 18; ++j) accA[j * kBlock + threadIdx.x] = accB[j * kBlock + threadIdx.x] = T(0);
+#pragma unroll 1
+            for (int nn = 0; nn < 3; ++nn) {
+                const int nu = nn + (nn >= mu);
+                const int Pl = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
+                const int fo = dual_plane(Pl) * ra.V;
+                const T sig = T((nu > mu ? 1 : -1) * dual_sign(Pl));
+                theta_loop_lds<T, 1>(ra, Ub, Fb, fo, x, d1, mu, nu, p, h, cb, mcb, cx<T>{sig * ct.re, sig * ct.im},
+                                     accA, accB);
+                __builtin_amdgcn_sched_barrier(0);
+                theta_loop_lds<T, -1>(ra, Ub, Fb, fo, x, d1, mu, nu, p, h, cb, mcb,
+                                      cx<T>{-sig * ct.re, -sig * ct.im}, accA, accB);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            A = lds_acc_get(accA);
+            B = lds_acc_get(accB);
+        } else
 #pragma unroll 1
         for (int nn = 0; nn < 3; ++nn) {
             const int nu = nn + (nn >= mu);
             const int Pl = mu < nu ? plane_of(mu, nu) : plane_of(nu, mu);
             const int fo = dual_plane(Pl) * ra.V;
-            // The dual clover matrices at d1 = x + mu and at x do not depend on
-            // the sign.  FP64 loads X1 once per plane (its overflow registers
-            // hold it) and, since cts changes sign with s, multiplies X0 once
-            // per plane: sum_s cts_s P_s X0 = cts_+ (P_+ - P_-) X0, and the same
-            // for X0 P'_s.  FP32 would spill and takes both per sign.
-            constexpr bool kHoist = sizeof(T) == 8;
-            mat3<T> X1 = m_zero<T>(), Dp = m_zero<T>(), Da = m_zero<T>();
-            if (kHoist && th) X1 = load_mat(Fb, fo + link_off(ra, 0, d1), fs);
-            // FP64: the s = -1 walk's first two matrices, loaded while the s = +1
-            // walk finishes (one wave per SIMD leaves no other wave to cover
-            // their latency)
-            mat3<T> ubN = m_zero<T>(), X3N = m_zero<T>();
             // unrolled over the sign: a compile-time s selects the raw link or its
             // adjugate
 #pragma unroll
             for (int si = 0; si < 2; ++si) {
                 const int s = si ? -1 : 1;
-                // FP64: scheduling barriers keep the walk's stages (and the two
-                // signs) from pulling every load forward at once
-                if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
                 const Site d3 = site_move(ra, x, nu, s);
                 const Site d2 = site_move(ra, d1, nu, s);
                 // e1 = U_nu(d1) (s>0) or U_nu(d2)^-1, e2 = U_mu(d3)^-1, e3 = U_nu(x)^-1 (s>0) or U_nu(d3)
@@ -455,25 +534,12 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                     // adj(ub) has e2^-1 = ub / det ub, and e1^-1 is adj(ua) / det ua
                     // (s > 0) or ua / det ua (s < 0, e1 = adj(ua)); exact for any
                     // links, not only det U = 1.
-                    mat3<T> ub, X3;
-                    if (kHoist && si == 1) {
-                        ub = ubN;
-                        X3 = X3N;
-                    } else {
-                        ub = load_mat(Ub, link_off(ra, mu, d3), us);
-                        X3 = load_mat(Fb, fo + link_off(ra, 0, d3), fs);
-                    }
-                    // (FP64: the next stage's link is requested with this one's)
-                    mat3<T> ua;
-                    if constexpr (kHoist) ua = load_mat(Ub, oa, us);
+                    const mat3<T> ub = load_mat(Ub, link_off(ra, mu, d3), us);
+                    const mat3<T> X3 = load_mat(Fb, fo + link_off(ra, 0, d3), fs);
                     const mat3<T> e2 = m_adj(ub);
                     mat3<T> Y = (e2 * X3) * ub;
                     Y = m_scale(Y, inv_det(ub, e2)) + load_mat(Fb, fo + link_off(ra, 0, d2), fs);
-                    if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
-                    if constexpr (!kHoist) ua = load_mat(Ub, oa, us);
-                    const int o3 = link_off(ra, nu, s > 0 ? x : d3);
-                    mat3<T> e3;
-                    if constexpr (kHoist) e3 = load_mat(Ub, o3, us);
+                    const mat3<T> ua = load_mat(Ub, oa, us);
                     const mat3<T> ua_adj = m_adj(ua);
                     const cx<T> ida = inv_det(ua, ua_adj);
                     mat3<T> e1, e1i;
@@ -485,15 +551,8 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                         e1i = ua;
                     }
                     const mat3<T> R = e1 * e2;
-                    mat3<T> Q = m_scale((e1 * Y) * e1i, ida) +
-                                (kHoist ? X1 : load_mat(Fb, fo + link_off(ra, 0, d1), fs));
-                    if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
-                    if constexpr (!kHoist) e3 = load_mat(Ub, o3, us);
-                    if (kHoist && si == 0) {
-                        const Site d3m = site_move(ra, x, nu, -1);
-                        ubN = load_mat(Ub, link_off(ra, mu, d3m), us);
-                        X3N = load_mat(Fb, fo + link_off(ra, 0, d3m), fs);
-                    }
+                    mat3<T> Q = m_scale((e1 * Y) * e1i, ida) + load_mat(Fb, fo + link_off(ra, 0, d1), fs);
+                    mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
                     if (s > 0) e3 = m_adj(e3);
                     const mat3<T> Pm = R * e3;
                     const mat3<T> Pa = m_adj(Pm);
@@ -502,27 +561,10 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 8 && THETA) ? 1 : 2) k_d
                     Q = m_scale(Q, cts);
                     m_mac(A, Q, Pm);
                     m_mac(B, Pa, Q);
-                    if constexpr (kHoist) {
-                        if (s > 0) {
-                            Dp = Pm;
-                            Da = Pa;
-                        } else {
-                            Dp = Dp - Pm;
-                            Da = Da - Pa;
-                        }
-                    } else {
-                        const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
-                        m_mac(A, Pm, X0s);
-                        m_mac(B, X0s, Pa);
-                    }
+                    const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
+                    m_mac(A, Pm, X0s);
+                    m_mac(B, X0s, Pa);
                 }
-            }
-            if (kHoist && th) {
-                __builtin_amdgcn_sched_barrier(0);
-                const T sig = T((nu > mu ? 1 : -1) * dual_sign(Pl));
-                const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cx<T>{sig * ct.re, sig * ct.im});
-                m_mac(A, Dp, X0s);
-                m_mac(B, X0s, Da);
             }
         }
         if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);

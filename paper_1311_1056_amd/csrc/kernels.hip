@@ -588,6 +588,33 @@ __global__ void __launch_bounds__(kBlock, 2) k_drift(const KArgs ka)
     CLGC_END_BLOCKS
 }
 
+// d^(-1/3) on the principal branch.  The updated link's determinant differs
+// from 1 only by rounding (the exponential of a traceless matrix has
+// determinant 1), so d = 1 + delta with |delta| ~ 1e-16 in FP64 and ~1e-7
+// from FP32 links: for |delta| < 2^-12 the binomial series of
+// (1 + delta)^(-1/3) to delta^5 is exact to 2e-23 and replaces the
+// logarithm, arctangent, exponential and sine/cosine; otherwise those are
+// evaluated.
+__device__ __forceinline__ cx<double> det_renorm_factor(cx<double> d)
+{
+    const cx<double> dl = {d.re - 1.0, d.im};
+    if (fabs(dl.re) < 0x1p-13 && fabs(dl.im) < 0x1p-13) {
+        // binomial coefficients of (1 + x)^(-1/3): -1/3, 2/9, -14/81, 35/243, -91/729
+        cx<double> w = {-91.0 / 729.0, 0.0};
+        w = cfma(w, dl, cx<double>{35.0 / 243.0, 0.0});
+        w = cfma(w, dl, cx<double>{-14.0 / 81.0, 0.0});
+        w = cfma(w, dl, cx<double>{2.0 / 9.0, 0.0});
+        w = cfma(w, dl, cx<double>{-1.0 / 3.0, 0.0});
+        return cfma(w, dl, cx<double>{1.0, 0.0});
+    }
+    const double lr = -log(sqrt(fma(d.re, d.re, d.im * d.im))) / 3.0;
+    const double ph = -atan2(d.im, d.re) / 3.0;
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    const double mg = exp(lr);
+    return {mg * cs, mg * sn};
+}
+
 // ---------------------------------------------------------------------------
 // Langevin update: U <- exp(i (eps K + sqrt(eps) eta_a lambda_a)) U, then
 // U <- U det(U)^{-1/3} in FP64.
@@ -677,13 +704,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
             const mat3<T> U = load_mat((const cx<T>*)ra.U, t, 4 * ra.V);
             // det renormalisation in FP64 on the principal branch
             const mat3<double> W = m_to_double(R * U);
-            const cx<double> d = m_det(W);
-            const double lr = -log(sqrt(fma(d.re, d.re, d.im * d.im))) / 3.0;
-            const double ph = -atan2(d.im, d.re) / 3.0;
-            double sn, cs;
-            sincos(ph, &sn, &cs);
-            const double mg = exp(lr);
-            const cx<double> w = {mg * cs, mg * sn};
+            const cx<double> w = det_renorm_factor(m_det(W));
             const mat3<T> Un = m_cast_from<T>(m_scale(W, w));
             store_mat((cx<T>*)ra.U, t, 4 * ra.V, Un);
             un += (double)m_norm2(Un);

@@ -96,6 +96,27 @@ def test_langevin_step_matches_oracle(cl, orc, adaptive, theta):
     lat.close()
 
 
+@pytest.mark.parametrize("c3", [1.0 + 3e-5 - 4e-5j, 1.3 * np.exp(0.9j)])
+def test_update_renormalises_any_determinant(cl, orc, c3):
+    """Links whose determinant is c3 != 1 before the step: the update must
+    still land on det U = 1 by the principal cube root, whether |det - 1| is
+    inside the range of the kernel's short series (first case) or far
+    outside it (second)."""
+    say("renorm", c3)
+    dims = (4, 4, 2, 4)
+    U = orc.init_links(dims, 7, 0.3, 0.05)
+    U = np.ascontiguousarray((U.view(np.complex128) * complex(c3) ** (1.0 / 3.0)).view(np.float64))
+    lat = cl.Lattice(dims, 6.0, 0.5, cl.CL_FP64, seed=7)
+    lat.set_links(U)
+    W = U.copy()
+    lat.langevin_step(1e-2, adaptive=False)
+    orc.langevin_step(dims, W, 6.0, 0.5, 7, 0, 1e-2, False)
+    got = lat.get_links()
+    assert relerr(got, W) < TOL
+    assert np.max(np.abs(np.linalg.det(got.view(np.complex128).reshape(-1, 3, 3)) - 1.0)) < 1e-13
+    lat.close()
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_gauge_cool_matches_oracle(cl, orc, mode):
     say("cool mode", mode)

@@ -218,10 +218,13 @@ def roofline(res, precision, theta):
     return rfs[0], kernels, rfs
 
 
-def step_roofline(res, precision, theta, n_cool):
+def step_roofline(res, precision, theta, n_cool, dims=None):
     """The whole CL step against the byte floor (one read and one write of the
     link field for the update and for each of the n_cool cooling steps) and
-    against the VALU (the algorithmic flops of the step's kernels)."""
+    against the VALU (the algorithmic flops of the step's kernels).  With
+    counter runs of the current kernels for this lattice, also the bytes the
+    step's kernels actually moved (FETCH_SIZE + WRITE_SIZE per launch times
+    launches per step, re-fetches included) over the step time."""
     rs = 8 if precision == "fp64" else 4
     V = res["V"]
     t = res["ms_per_step"] * 1e-3
@@ -237,7 +240,27 @@ def step_roofline(res, precision, theta, n_cool):
             "achieved_TFLOPs": round(flops / t / 1e12, 2), "peak_TFLOPs": peak,
             "hbm_bound_ms": round(1e3 * t_hbm, 4), "valu_bound_ms": round(1e3 * t_valu, 4),
             "binding_roof": "hbm" if t_hbm >= t_valu else "valu",
-            "frac_of_binding_roof": round(max(t_hbm, t_valu) / t, 4), "ms_per_step": round(1e3 * t, 4)}
+            "frac_of_binding_roof": round(max(t_hbm, t_valu) / t, 4), "ms_per_step": round(1e3 * t, 4),
+            **measured_step_traffic(precision, dims, theta, n_cool, t)}
+
+
+def measured_step_traffic(precision, dims, theta, n_cool, t):
+    """Counter-measured bytes per step and their rate, or nulls when a kernel
+    of the step has no counter run on the current source."""
+    out = {"traffic_bytes_per_step": None, "traffic_GBs": None, "frac_hbm_traffic": None}
+    if dims is None:
+        return out
+    launches = {"k_drift": 1, "k_update": 1, "k_cool_omega": n_cool, "k_cool_apply": n_cool}
+    if theta:
+        launches["k_clover"] = 1
+    total = 0
+    for k, n in launches.items():
+        b = traffic_for(k, precision, dims)
+        if b is None:
+            return out
+        total += n * b
+    return {"traffic_bytes_per_step": total, "traffic_GBs": round(total / t / 1e9, 1),
+            "frac_hbm_traffic": round(total / t / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 _COPY_CACHE = {}
@@ -447,7 +470,8 @@ def large_lattice(args):
     res = run_gpu(a, "fp64")
     rf, kernels, rfs = roofline(res, "fp64", args.theta)
     out = {"lattice": "32x32x32x32", "value": round(res["value"], 1), "unit": "link-updates/s",
-           "ms_per_step": round(res["ms_per_step"], 4), "steps": a.steps, "roofline": rf, "rooflines": rfs}
+           "ms_per_step": round(res["ms_per_step"], 4), "steps": a.steps, "roofline": rf, "rooflines": rfs,
+           "step_roofline": step_roofline(res, "fp64", args.theta, args.ncool, (32, 32, 32, 32))}
     # one GPU's share of a 32^4 lattice split in two along x3 (the kernels at
     # that shape, periodic here; the halo exchange of a real split is not built)
     b = with_args(args, dims="32,32,32,16", steps=10, warmup=2)
@@ -803,6 +827,7 @@ def main():
     if args.chain_only:
         print(json.dumps({"chain": chain_workload(args)}), flush=True)
         return
+    dims = tuple(int(x) for x in args.dims.split(","))
     res = run_gpu(args, args.precision)
     rf, kernels, rfs = roofline(res, args.precision, args.theta)
     progress(f"main workload: {res['value'] / 1e6:.1f} M link-updates/s")
@@ -826,7 +851,7 @@ def main():
                    "lattice": args.dims.replace(",", "x"), "precision": args.precision,
                    "parallelism": "single GPU"},
         "roofline": rf,
-        "step_roofline": step_roofline(res, args.precision, args.theta, args.ncool),
+        "step_roofline": step_roofline(res, args.precision, args.theta, args.ncool, dims),
         "rooflines": rfs,
         "kernels": kernels,
         "observables_after": {"plaq": [res["obs"]["plaq"].real, res["obs"]["plaq"].imag],
@@ -838,7 +863,7 @@ def main():
         mrf, mk, mrfs = roofline(mx, "mixed", args.theta)
         out["mixed"] = {"value": round(mx["value"], 1), "ms_per_step": round(mx["ms_per_step"], 4),
                         "dtype": "f32 links/drift/cooling, f64 det renorm, reductions, measurement and control",
-                        "roofline": mrf, "step_roofline": step_roofline(mx, "mixed", args.theta, args.ncool),
+                        "roofline": mrf, "step_roofline": step_roofline(mx, "mixed", args.theta, args.ncool, dims),
                         "rooflines": mrfs}
         # the same workload recording every step's observables on the device
         rc = run_gpu(args, "fp64", with_timing=False, record=True)

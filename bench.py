@@ -77,13 +77,15 @@ def algorithmic_cost(kind, V, rs, theta):
     L = 4 * V
     mat = 18 * rs
     prod, adj, hprod, hexp = 216, 126, 162, 500
-    om = (V // 2) * mat  # the even sites' staged Omega pairs, in the link type
+    # the even sites' staged transforms in the link type: Omega alone in FP64
+    # (the applying kernel inverts it), Omega - 1 and Omega^-1 - 1 in FP32
+    om = (V // 2) * (9 if rs == 8 else 18) * rs
     if kind == "cool_omega":
-        # read every link once, write Omega and Omega^-1 (18 reals) per even site;
+        # read every link once, write the staged transform per even site;
         # per even site: 8 U U^dagger-type Hermitian products (54 flops) + one pair
         return {"bytes": L * mat + om, "flops": (V // 2) * (8 * 54 + hexp)}
     if kind == "cool_apply":
-        # read and write every link once, read Omega pairs; per link: even transform,
+        # read and write every link once, read the staged transforms; per link: even transform,
         # odd transform (Hermitian products), per odd site: G and one exponential pair
         return {"bytes": L * 2 * mat + om,
                 "flops": L * 2 * hprod + (V // 2) * (8 * 54 + hexp)}

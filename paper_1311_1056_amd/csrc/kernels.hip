@@ -958,6 +958,47 @@ __device__ __forceinline__ mat3<T> mul_h(const mat3<T>& U, const herm3<T>& H)
 template <typename T>
 constexpr bool kCoolDelta = sizeof(T) == 4;
 
+// FP64 stages Omega alone (9 reals per even site) and the applying kernel
+// inverts it (h_inverse: Omega is Hermitian positive definite and near 1,
+// so the adjugate over the determinant is accurate to rounding); the
+// cooling pair is bound by its bytes there, and this drops a ninth of them.
+// FP32 stages both Omega - 1 and Omega^-1 - 1, each formed without
+// cancellation by the series.
+template <typename T>
+constexpr bool kStageInverse = kCoolDelta<T>;
+
+// H^-1 for Hermitian H with det H > 0: adj(H) / det H, Hermitian again
+template <typename T>
+__device__ __forceinline__ herm3<T> h_inverse(const herm3<T>& H)
+{
+    herm3<T> a;
+    a.d0 = H.d1 * H.d2 - norm2(H.u12);
+    a.d1 = H.d0 * H.d2 - norm2(H.u02);
+    a.d2 = H.d0 * H.d1 - norm2(H.u01);
+    a.u01 = H.u02 * conj(H.u12) - H.d2 * H.u01;
+    a.u02 = H.u01 * H.u12 - H.d1 * H.u02;
+    a.u12 = H.u02 * conj(H.u01) - H.d0 * H.u12;
+    const T det = H.d0 * a.d0 + (H.u01.re * a.u01.re + H.u01.im * a.u01.im) +
+                  (H.u02.re * a.u02.re + H.u02.im * a.u02.im);
+    const T r = T(1) / det;
+    a.d0 *= r;
+    a.d1 *= r;
+    a.d2 *= r;
+    a.u01 = r * a.u01;
+    a.u02 = r * a.u02;
+    a.u12 = r * a.u12;
+    return a;
+}
+
+// Omega^-1 of the even site from what the omega kernel staged at value
+// offset 9 (the inverse itself) or 0 (Omega, inverted here)
+template <typename T>
+__device__ __forceinline__ herm3<T> staged_inverse(const herm3<T>& S)
+{
+    if constexpr (kStageInverse<T>) return S;
+    else return h_inverse(S);
+}
+
 // The even half-sweep on an odd site's lane, Uf Omega^-1 (the even site at
 // the link's end) and Omega Ub (the even site at its start).  FP64 transforms
 // Uf and Ub in place.  FP32 keeps the entering links and returns the small
@@ -1002,12 +1043,12 @@ __device__ __forceinline__ void odd_transforms(const mat3<T>& Uf, const mat3<T>&
     }
 }
 
-// the 18 reals of the staged (Omega, Omega^-1) of even site h: value j at
-// OM[j * Vh + h], in the link type
+// the staged transform of even site h, value j at OM[j * Vh + h] in the link
+// type: 18 reals (Omega, Omega^-1) where kStageInverse, else the 9 of Omega
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t omega_rsrc(const RunArgs& ra)
 {
-    const uint32_t bytes = 18u * (uint32_t)ra.Vh * (uint32_t)sizeof(T);
+    const uint32_t bytes = (kStageInverse<T> ? 18u : 9u) * (uint32_t)ra.Vh * (uint32_t)sizeof(T);
     return __builtin_amdgcn_make_buffer_rsrc(ra.K, (short)0, (int)bytes, kBufferWord3);
 }
 
@@ -1185,11 +1226,11 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
                     cr->hist_n = iter + 1;
                 }
             }
-            // wavefront 0 forms Omega, wavefront 1 Omega^-1 (2 and 3 only
-            // contribute their shares)
+            // wavefront 0 forms Omega, wavefront 1 Omega^-1 where it is staged
+            // (the others only contribute their shares)
             const T coef = T(-4.0 * ra.eps_c * alpha_ad);
             const herm3<T> Gx = site_sum(G, sh, buf);
-            if (mu < 2) {
+            if (mu < (kStageInverse<T> ? 2 : 1)) {
                 herm3<T> E;
                 site_omega_one(Gx, mu == 1 ? -coef : coef, E);
                 if (ok && lane_ok) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
@@ -1230,7 +1271,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
                 const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
                 Uf = load_mat(Uc, of, 4 * ra.V);
                 Ub = load_mat(Uc, ob, 4 * ra.V);
-                even_transforms(Uf, Ub, load_herm<T>(om, site_half(ra, yf), ra.Vh, 9),
+                even_transforms(Uf, Ub,
+                                staged_inverse(load_herm<T>(om, site_half(ra, yf), ra.Vh, kStageInverse<T> ? 9 : 0)),
                                 load_herm<T>(om, site_half(ra, yb), ra.Vh, 0), Tf, Tb);
                 h_add_uudag(G, half_swept(Uf, Tf));
                 h_sub_udagu(G, half_swept(Ub, Tb));
@@ -1330,7 +1372,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
                 h_sub_udagu(G, Ab);
             }
             const herm3<T> Gx = site_sum(G, sh, buf);
-            if (mu < 2) {
+            if (mu < (kStageInverse<T> ? 2 : 1)) {
                 herm3<T> E;
                 site_omega_one(Gx, mu == 1 ? -coef : coef, E);
                 if (ok && lok) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
@@ -1345,7 +1387,8 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
 }
 
 // lane (h, mu) of chunk c: U_mu(y), U_mu(y - mu) of odd site h and the even
-// transforms they take (Omega^-1 of y + mu, Omega of y - mu)
+// transforms they take (what is staged for Omega^-1 of y + mu -- the inverse
+// itself or Omega, see staged_inverse -- and Omega of y - mu)
 template <typename T>
 struct ApplyIn {
     mat3<T> Uf, Ub;
@@ -1367,7 +1410,7 @@ __device__ __forceinline__ void apply_loads(const RunArgs& ra, int c, ApplyIn<T>
         const cx<T>* __restrict__ Uc = (const cx<T>*)ra.U;
         const __amdgpu_buffer_rsrc_t om = omega_rsrc<T>(ra);
         in.Uf = load_mat(Uc, in.of, 4 * ra.V);
-        in.Eif = load_herm<T>(om, site_half(ra, yf), ra.Vh, 9);
+        in.Eif = load_herm<T>(om, site_half(ra, yf), ra.Vh, kStageInverse<T> ? 9 : 0);
         in.Eb = load_herm<T>(om, site_half(ra, yb), ra.Vh, 0);
         in.Ub = load_mat(Uc, in.ob, 4 * ra.V);
     }
@@ -1399,7 +1442,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int it
             herm3<T> G = h_zero<T>();
             mat3<T> Uf = cur.Uf, Ub = cur.Ub, Tf, Tb;
             if (cur.lok) {
-                even_transforms(Uf, Ub, cur.Eif, cur.Eb, Tf, Tb);
+                even_transforms(Uf, Ub, staged_inverse(cur.Eif), cur.Eb, Tf, Tb);
                 h_add_uudag(G, half_swept(Uf, Tf));
                 h_sub_udagu(G, half_swept(Ub, Tb));
             }

@@ -148,13 +148,18 @@ __device__ __forceinline__ double wave_cool_sum(const RunArgs& ra) { return wave
         }                                                                      \
     } else {                                                                   \
         const BatchHdr* __restrict__ hdr_ = ka.hdr;                            \
+        /* the run table does not change during a launch: read through the    \
+           constant address space, like the kernel arguments, so that its     \
+           fields are not re-read after every store of the body */            \
+        const __attribute__((address_space(4))) RunArgs* runs4_ =              \
+            (const __attribute__((address_space(4))) RunArgs*)ka.runs;          \
         const int total_ = hdr_->total[kind_];                                 \
         const int q_ = (total_ + kXcds - 1) / kXcds;                           \
         for (int gb0_ = blockIdx.x; gb0_ < kXcds * q_; gb0_ += gridDim.x) {    \
             const int gb_ = logical_block(gb0_, total_);                       \
             if (gb_ >= total_) continue;                                       \
             const int run_ = find_run(hdr_, kind_, gb_);                       \
-            body_(ka.runs[run_], gb_ - hdr_->begin[kind_][run_]);              \
+            body_(*(const RunArgs*)&runs4_[run_], gb_ - hdr_->begin[kind_][run_]); \
         }                                                                      \
     }
 

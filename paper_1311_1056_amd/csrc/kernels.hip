@@ -147,10 +147,11 @@ __device__ __forceinline__ double wave_cool_sum(const RunArgs& ra) { return wave
             if (gb_ < total_) body_(ka.one, gb_);                              \
         }                                                                      \
     } else {                                                                   \
-        const BatchHdr* __restrict__ hdr_ = ka.hdr;                            \
-        /* the run table does not change during a launch: read through the    \
-           constant address space, like the kernel arguments, so that its     \
-           fields are not re-read after every store of the body */            \
+        /* the batch tables do not change during a launch: read through the   \
+           constant address space, like the kernel arguments (scalar loads,   \
+           and no re-reads of RunArgs fields after every store of the body) */ \
+        const __attribute__((address_space(4))) BatchHdr* hdr_ =               \
+            (const __attribute__((address_space(4))) BatchHdr*)ka.hdr;          \
         const __attribute__((address_space(4))) RunArgs* runs4_ =              \
             (const __attribute__((address_space(4))) RunArgs*)ka.runs;          \
         const int total_ = hdr_->total[kind_];                                 \

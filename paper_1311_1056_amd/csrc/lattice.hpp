@@ -323,7 +323,7 @@ __host__ __device__ constexpr int dual_plane(int P) { return 5 - P; }
 __host__ __device__ constexpr int dual_sign(int P) { return (P == 1 || P == 4) ? -1 : 1; }
 
 // find the run that owns logical block b of a kind (uniform per block)
-__device__ __forceinline__ int find_run(const BatchHdr* __restrict__ hdr, int kind, int b)
+__device__ __forceinline__ int find_run(const __attribute__((address_space(4))) BatchHdr* hdr, int kind, int b)
 {
     int lo = 0, hi = hdr->nrun - 1;
     while (lo < hi) {

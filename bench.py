@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--served-runs", type=int, default=256, help="runs in the served mix (0: skip)")
     ap.add_argument("--served-budget-mb", type=int, default=2048)
+    ap.add_argument("--served-steps-per-call", type=int, default=4,
+                    help="batch steps per server call (one wait for the GPU per call)")
     ap.add_argument("--chain-only", action="store_true",
                     help="only run the SU(2) Polyakov-chain leg (for profiling its kernel)")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -404,7 +406,7 @@ def served(args, capacity_lus, n_runs, load, prec=None):
             srv.submit(r["dims"], r["beta"], r["theta"], r["prec"], r["seed"], r["n_steps"], r["eps0"], True,
                        r["n_cool"], r["eps0"], 1.0, cl.CL_ALPHA_UNORM, tag=i)
             i += 1
-        a, p = srv.step()
+        a, p = srv.step(args.served_steps_per_call)
         results += srv.poll()
         if a == 0 and p == 0 and i < len(runs):
             time.sleep(max(0.0, min(arrivals[i] - (time.perf_counter() - t0), 0.01)))
@@ -418,7 +420,7 @@ def served(args, capacity_lus, n_runs, load, prec=None):
             "queue_wait_s_p50": round(st["wait_s_p50"], 3), "queue_wait_s_p99": round(st["wait_s_p99"], 3),
             "makespan_s": round(makespan, 2), "gpu_busy_s": round(st["busy_s"], 2),
             "batch_steps": st["batch_steps"], "load": load, "arrival_rate_runs_per_s": round(rate, 3),
-            "budget_bytes": args.served_budget_mb << 20,
+            "budget_bytes": args.served_budget_mb << 20, "steps_per_call": args.served_steps_per_call,
             "mix": "6^4, 8^4, 12^4, 16^4, 8^3x16, 24^3x8; beta U[5.7,6.2]; theta U[0,2]; 50-500 steps; "
                    f"1-20 D1 cooling steps; eps0 U[1e-3,1e-2]; {PREC_NAMES[prec]}; Poisson arrivals"}
 
@@ -587,7 +589,7 @@ def alone_vs_batched(args, n=32):
                    r["n_cool"], r["eps0"], 1.0, cl.CL_ALPHA_UNORM, tag=i)
     res = []
     while len(res) < n:
-        srv.step()
+        srv.step(args.served_steps_per_call)
         res += srv.poll()
     tb = time.perf_counter() - t0
     srv.close()

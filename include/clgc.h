@@ -281,8 +281,17 @@ cl_status cl_server_create(void* arena, size_t arena_bytes, void* hip_stream, cl
 cl_status cl_server_submit(cl_server* srv, const cl_run_desc* run, uint64_t* run_id);
 /* Admit what fits, advance every active run by one step, retire finished
  * runs.  Waits for the GPU at the end of the step.  n_active / n_pending may
- * be NULL. */
+ * be NULL.  The same as cl_server_steps(srv, 1, ...). */
 cl_status cl_server_step(cl_server* srv, int* n_active, int* n_pending);
+/* Admit what fits, then advance every active run by n batch steps with one
+ * wait for the GPU at the end, n = min(max_steps, the fewest steps any
+ * active run has left), so that no run goes past its last step; retire
+ * finished runs.  Runs submitted meanwhile are admitted by the next call.
+ * A run's step_ms samples are the call's wall time over n.  A run that runs
+ * away during the call stops advancing at that point (its steps_done is its
+ * own step counter) and is retired at the end of the call.  CL_EINVAL if
+ * max_steps < 1. */
+cl_status cl_server_steps(cl_server* srv, int max_steps, int* n_active, int* n_pending);
 /* Move up to cap finished results into out (oldest first). */
 cl_status cl_server_poll(cl_server* srv, cl_run_result* out, int cap, int* n_done);
 cl_status cl_server_stats_get(cl_server* srv, cl_server_stats* out);

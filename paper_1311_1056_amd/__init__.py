@@ -121,6 +121,7 @@ def _load():
         "cl_server_create": [vp, sz, vp, P(vp)],
         "cl_server_submit": [vp, P(cl_run_desc), P(ctypes.c_uint64)],
         "cl_server_step": [vp, P(ctypes.c_int), P(ctypes.c_int)],
+        "cl_server_steps": [vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int)],
         "cl_server_poll": [vp, P(cl_run_result), ctypes.c_int, P(ctypes.c_int)],
         "cl_server_stats_get": [vp, P(cl_server_stats)],
         "cl_server_destroy": [vp],
@@ -355,9 +356,12 @@ class Server:
         _check(lib.cl_server_submit(self.handle, ctypes.byref(d), ctypes.byref(rid)))
         return rid.value
 
-    def step(self):
+    def step(self, max_steps=1):
         a, p = ctypes.c_int(), ctypes.c_int()
-        _check(lib.cl_server_step(self.handle, ctypes.byref(a), ctypes.byref(p)))
+        if max_steps == 1:
+            _check(lib.cl_server_step(self.handle, ctypes.byref(a), ctypes.byref(p)))
+        else:
+            _check(lib.cl_server_steps(self.handle, int(max_steps), ctypes.byref(a), ctypes.byref(p)))
         return a.value, p.value
 
     def poll(self, cap=256):

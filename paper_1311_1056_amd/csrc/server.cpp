@@ -317,39 +317,49 @@ cl_status cl_server_submit(cl_server* s, const cl_run_desc* run, uint64_t* run_i
     return CL_OK;
 }
 
-cl_status cl_server_step(cl_server* s, int* n_active, int* n_pending)
+cl_status cl_server_steps(cl_server* s, int max_steps, int* n_active, int* n_pending)
 {
     if (!s) return fail(CL_EINVAL, "server is NULL");
+    if (max_steps < 1) return fail(CL_EINVAL, "max_steps = %d, must be >= 1", max_steps);
     const double t_begin = s->now();
     cl_status st = admit(s);
     if (st) return st;
     if (!s->active.empty()) {
         if (s->dirty && (st = upload_tables(s)) != CL_OK) return st;
         if ((st = ensure_graph(s)) != CL_OK) return st;
-        HIP_TRY(hipGraphLaunch(s->graph, s->stream));
+        // as many batch steps as the call allows without taking any run past
+        // its last step; one synchronisation for all of them
+        int n = max_steps;
+        for (const auto& r : s->active) n = std::min(n, r->desc.n_steps - r->steps_done);
+        n = std::max(n, 1);
+        for (int k = 0; k < n; ++k) HIP_TRY(hipGraphLaunch(s->graph, s->stream));
         for (int g = 0; g < 2; ++g)
             if (!s->group[g].empty())
                 HIP_TRY(hipMemcpyAsync(s->h_gather[g], s->d_gather[g], sizeof(GatherRec) * s->group[g].size(),
                                        hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
-        const float ms = (float)(1e3 * (s->now() - t_begin));
-        s->busy_s += ms * 1e-3;
-        ++s->batch_steps;
+        const double ms_all = 1e3 * (s->now() - t_begin);
+        const float ms = (float)(ms_all / n);  // per batch step
+        s->busy_s += ms_all * 1e-3;
+        s->batch_steps += n;
         // per-run bookkeeping; collect retirements first (retire edits the groups)
         std::vector<std::pair<Run*, int>> finished;
         for (int g = 0; g < 2; ++g)
             for (size_t i = 0; i < s->group[g].size(); ++i) {
                 Run* r = s->group[g][i];
                 const GatherRec& gr = s->h_gather[g][i];
-                r->step_ms.push_back(ms);
-                s->all_step_ms.push_back(ms);
-                if (gr.status != ST_OK) {
-                    finished.push_back({r, CL_ENONFINITE});
-                    continue;
+                // the run's own step counter: a run stops advancing when its
+                // status leaves ST_OK (the kernels then leave its links as
+                // they are), so it counts the steps actually taken
+                const int adv = (int)(gr.step - r->steps_done);
+                for (int k = 0; k < adv; ++k) {
+                    r->step_ms.push_back(ms);
+                    s->all_step_ms.push_back(ms);
                 }
-                ++r->steps_done;
-                s->link_updates += 4 * r->V;
-                if (r->steps_done >= r->desc.n_steps) finished.push_back({r, CL_OK});
+                r->steps_done += adv;
+                s->link_updates += 4 * r->V * adv;
+                if (gr.status != ST_OK) finished.push_back({r, CL_ENONFINITE});
+                else if (r->steps_done >= r->desc.n_steps) finished.push_back({r, CL_OK});
             }
         for (auto& f : finished) {
             size_t idx = 0;
@@ -360,6 +370,11 @@ cl_status cl_server_step(cl_server* s, int* n_active, int* n_pending)
     if (n_active) *n_active = (int)s->active.size();
     if (n_pending) *n_pending = (int)s->pending.size();
     return CL_OK;
+}
+
+cl_status cl_server_step(cl_server* s, int* n_active, int* n_pending)
+{
+    return cl_server_steps(s, 1, n_active, n_pending);
 }
 
 cl_status cl_server_poll(cl_server* s, cl_run_result* out, int cap, int* n_done)

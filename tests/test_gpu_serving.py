@@ -16,10 +16,10 @@ def cl():
     return cl
 
 
-def drain(srv, max_steps=10000):
+def drain(srv, max_calls=10000, per_call=1):
     results = []
-    for _ in range(max_steps):
-        a, p = srv.step()
+    for _ in range(max_calls):
+        a, p = srv.step(per_call)
         results += srv.poll()
         if a == 0 and p == 0:
             break
@@ -180,4 +180,31 @@ def test_served_runs_match_oracle(cl, orc):
     # taken links are released; a second take fails
     with pytest.raises(cl.ClError):
         srv.take_links(ids[0], ORACLE_RUNS[0]["dims"])
+    srv.close()
+
+
+def test_several_steps_per_call(cl):
+    """cl_server_steps: up to 4 batch steps per wait, never past a run's last
+    step; every run ends with its own step count and the results of the runs
+    done alone; a run that runs away mid-call is retired with the steps it
+    took; max_steps < 1 is rejected."""
+    srv = cl.Server(512 << 20)
+    for i, r in enumerate(RUNS):
+        submit(srv, r, i)
+    srv.submit((6, 6, 6, 6), 1e300, 1.0, 0, 999, n_steps=5, n_cool=2, tag=99)
+    res = {x["tag"]: x for x in drain(srv, per_call=4)}
+    assert res[99]["status"] == cl.CL_ENONFINITE and res[99]["steps_done"] == 0
+    for i, r in enumerate(RUNS):
+        got = res[i]
+        assert got["status"] == 0 and got["steps_done"] == r["n_steps"], (i, got["steps_done"])
+        ref = alone(cl, r)
+        for k in ("plaq", "q", "d", "eps"):
+            assert close(got["obs"][k], ref[k], r["prec"]), (i, k, got["obs"][k], ref[k])
+        assert got["obs"]["step"] == r["n_steps"]
+    st = srv.stats()
+    # fewer batch-step calls than steps: the longest run has 6 steps
+    assert st["finished"] == len(RUNS) + 1 and st["batch_steps"] >= max(r["n_steps"] for r in RUNS)
+    with pytest.raises(cl.ClError) as e:
+        srv.step(0)
+    assert e.value.status == cl.CL_EINVAL
     srv.close()

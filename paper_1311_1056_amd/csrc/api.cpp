@@ -231,18 +231,23 @@ cl_status enqueue_record(cl_lattice* lat)
 cl_status enqueue_step(cl_lattice* lat, bool fold)
 {
     const bool theta = lat->has_theta;
-    if (theta && !lat->F_valid) {
-        TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0));
+    // recording: the links entering this step are the ones the previous step
+    // left after its cooling.  FP64 with a theta term measures them with the
+    // step's own clover kernel (its first leaf is the plaquette) and a charge
+    // pass over the clover field it builds, summed before the update changes
+    // the control block; otherwise a measurement kernel runs first.
+    const bool rec_in_step = lat->record && theta && lat->prec == CL_FP64;
+    if (theta && (!lat->F_valid || rec_in_step)) {
+        TIMED(lat, CL_K_CLOVER, launch_clover(lat->L, lat->prec, 0, rec_in_step));
         lat->F_valid = true;
     }
-    // recording: the links entering this step are the ones the previous step
-    // left after its cooling, and with a theta term their clover field was
-    // just built for the drift
-    if (lat->record) {
+    if (rec_in_step) TIMED(lat, CL_K_MEASURE, launch_record_charge(lat->L));
+    if (lat->record && !rec_in_step) {
         cl_status st = enqueue_record(lat);
         if (st) return st;
     }
     TIMED(lat, CL_K_DRIFT, launch_drift(lat->L, lat->prec, theta));
+    if (rec_in_step) TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_RECORD_STEP, 0));
     TIMED(lat, CL_K_UPDATE, launch_update(lat->L, lat->prec));
     if (!fold || lat->args.n_cool == 0) TIMED(lat, CL_K_FINALIZE, launch_finalize(lat->L, FIN_UPDATE, 0));
     lat->F_valid = false;

@@ -34,8 +34,12 @@ hipError_t launch_init(const Launch& L, int prec, int perturbed, double sx, doub
 hipError_t launch_unorm(const Launch& L, int prec);
 hipError_t launch_unpack(const Launch& L, int prec, const double* aos);
 hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos);
-hipError_t launch_clover(const Launch& L, int prec, int only_theta);
+// record (single lattice, FP64 with a theta term): the clover kernel also
+// leaves the plaquette traces and link norms and launch_record_charge the
+// charge density, as partials for FIN_RECORD_STEP (layout at record_partial)
+hipError_t launch_clover(const Launch& L, int prec, int only_theta, bool record = false);
 hipError_t launch_drift(const Launch& L, int prec, bool theta);
+hipError_t launch_record_charge(const Launch& L);
 hipError_t launch_update(const Launch& L, int prec);
 // phase 0: even-site Omega (k_cool_omega); phase 1: apply both half-sweeps (k_cool_apply)
 hipError_t launch_cool(const Launch& L, int prec, int phase, int iter);
@@ -77,6 +81,6 @@ inline void blocks_per_kind(int V, int out[NKIND])
     out[KIND_DRIFT] = 8 * ((Vh + kBlock - 1) / kBlock);             // (region, mu, parity)
 }
 
-constexpr int kNumPartials = 7;  // the most partial values any kernel publishes
+constexpr int kNumPartials = 8;  // partial values per logical block of the widest kind
 
 }  // namespace clgc

@@ -62,6 +62,17 @@ __device__ __forceinline__ void store_partials(const RunArgs& ra, int kind, int 
     }
 }
 
+// Partials of a recorded step, FP64 with a theta term (the measurement
+// rides on the step's own clover kernel): value j of logical block b at
+// part[j * nblk[KIND_PLANE] + b].  The clover kernel leaves j = 1..4 (Tr P
+// re / im, Tr P^-1 re / im) and 5 (link norms), k_record_charge j = 6, 7 (the
+// clover bracket re / im, one block per 256 sites, fewer than the clover's
+// blocks); j = 0 stays the drift's own K_max partial, written in between.
+__device__ __forceinline__ double* record_partial(const RunArgs& ra, int j)
+{
+    return ra.part + (size_t)j * ra.nblk[KIND_PLANE];
+}
+
 // Fixed-order sum (or max) of n partials at p_in; valid in thread 0.  Each
 // thread issues eight independent loads before combining them, so the gather
 // costs a few memory round trips rather than one per loop trip.
@@ -286,9 +297,16 @@ __global__ void __launch_bounds__(kBlock) k_pack(const KArgs ka,
 
 template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock, 2) k_clover(const KArgs ka,
-                                                   int only_theta)
+                                                   int only_theta, int record)
 {
+    __shared__ double lds[5 * 4];
     CLGC_FOR_BLOCKS(KIND_PLANE)
+    // record (FP64): the first leaf is the plaquette of the plane at x; with
+    // the norm of one of the site's links in four of the six planes (mu's
+    // link in 01, 12, 23, the 3-link in 03) the blocks cover every plaquette
+    // and every link once
+    constexpr bool kRec = sizeof(T) == 8;
+    double rv[5] = {0, 0, 0, 0, 0};
     // logical block -> (region of 256 half-indices, plane, parity), regions major
     const int P = (lb % 12) >> 1, p = lb & 1;
     const int h = xcd_region_order(ra, lb / 12, ra.nblk[KIND_PLANE] / 12) * kBlock + (int)threadIdx.x;
@@ -311,7 +329,20 @@ __global__ void __launch_bounds__(kBlock, 2) k_clover(const KArgs ka,
             // U_mu(x), is loaded again (a cache hit)
             // U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^{-1}
             mat3<T> S = ldU<T>(ra, nu, x);
-            L = (ldU<T>(ra, mu, x) * ldU<T>(ra, nu, xpm)) * m_adj(S * ldU<T>(ra, mu, xpn));
+            const mat3<T> Umx = ldU<T>(ra, mu, x);
+            L = (Umx * ldU<T>(ra, nu, xpm)) * m_adj(S * ldU<T>(ra, mu, xpn));
+            if (kRec && record) {
+                const cx<T> tp = m_tr(L);
+                const cx<T> ti = (L.e[1][1] * L.e[2][2] - L.e[1][2] * L.e[2][1]) +
+                                 (L.e[0][0] * L.e[2][2] - L.e[0][2] * L.e[2][0]) +
+                                 (L.e[0][0] * L.e[1][1] - L.e[0][1] * L.e[1][0]);
+                rv[0] = tp.re;
+                rv[1] = tp.im;
+                rv[2] = ti.re;
+                rv[3] = ti.im;
+                if (P == 0 || P == 3 || P == 5) rv[4] = m_norm2(Umx);
+                else if (P == 2) rv[4] = m_norm2(S);
+            }
             F = L - m_adj(L);
             __builtin_amdgcn_sched_barrier(0);
             // U_nu(x) [U_nu(x-mu) U_mu(x-mu+nu)]^{-1} U_mu(x-mu)
@@ -350,6 +381,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_clover(const KArgs ka,
             F = F + (L - m_adj(L));
         }
         store_mat((cx<T>*)ra.F, tid_f, 6 * ra.V, F);
+    }
+    if (kRec && record) {
+        block_reduce<5>(rv, lds);
+        if (threadIdx.x == 0)
+            for (int j = 0; j < 5; ++j) record_partial(ra, 1 + j)[lb] = rv[j];
     }
     CLGC_END_BLOCKS
 }
@@ -1667,6 +1703,36 @@ __global__ void __launch_bounds__(kBlock) k_measure(const KArgs ka)
     CLGC_END_BLOCKS
 }
 
+// The charge density of a recorded FP64 step with a theta term, from the
+// clover field the step's clover kernel built for the links it measures: one
+// lane per site, Tr F01 F23 - Tr F02 F13 + Tr F03 F12 (re, im) into the record
+// partials 6 and 7 (record_partial).  Summed on the drift's own lanes it
+// pushed the drift past 256 registers (scratch), so it has its own launch.
+template <bool FAST>
+__global__ void __launch_bounds__(kBlock) k_record_charge(const KArgs ka)
+{
+    __shared__ double lds[2 * 4];
+    CLGC_FOR_BLOCKS(KIND_SITE)
+    double q[2] = {0.0, 0.0};
+    if (tid < ra.V) {
+        const cx<double>* __restrict__ Fb = (const cx<double>*)ra.F;
+#pragma unroll 1
+        for (int P = 0; P < 3; ++P) {
+            const cx<double> t = m_trmul(load_mat(Fb, P * ra.V + tid, 6 * ra.V),
+                                         load_mat(Fb, (5 - P) * ra.V + tid, 6 * ra.V));
+            const double sg = P == 1 ? -1.0 : 1.0;
+            q[0] += sg * t.re;
+            q[1] += sg * t.im;
+        }
+    }
+    block_reduce<2>(q, lds);
+    if (threadIdx.x == 0) {
+        record_partial(ra, 6)[lb] = q[0];
+        record_partial(ra, 7)[lb] = q[1];
+    }
+    CLGC_END_BLOCKS
+}
+
 // ---------------------------------------------------------------------------
 // finalize: one block per run sums (or maxes) the partials of the kernel that
 // just ran, in a fixed order, and updates the run's control block.
@@ -1749,16 +1815,26 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const KArgs ka, int what, i
             break;
         }
         case FIN_MEASURE:
-        case FIN_RECORD: {
+        case FIN_RECORD:
+        case FIN_RECORD_STEP: {
+            // the seven measurement sums (Tr P re / im, Tr P^-1 re / im, the
+            // clover bracket re / im, the link norms): from the measurement
+            // kernel, or from the recorded step's clover and drift kernels
             double o[7];
             for (int j = 0; j < 7; ++j) {
-                o[j] = gather_partials(ra, KIND_SITE, j, lds);
+                if (what == FIN_RECORD_STEP) {
+                    const int rj = j < 4 ? 1 + j : (j < 6 ? 2 + j : 5);
+                    const int n = j == 4 || j == 5 ? ra.nblk[KIND_SITE] : ra.nblk[KIND_PLANE];
+                    o[j] = gather_values(record_partial(ra, rj), n, lds);
+                } else {
+                    o[j] = gather_partials(ra, KIND_SITE, j, lds);
+                }
                 if (threadIdx.x == 0) c->obs[j] = o[j];
             }
             // the record entry of CL step n (1-based), measured on the links that
             // step left after its cooling (the measurement runs before step n + 1
             // or after a call's last step: either way the step counter is n)
-            if (what == FIN_RECORD && threadIdx.x == 0 && ok && ra.rec && c->step >= 1) {
+            if (what != FIN_MEASURE && threadIdx.x == 0 && ok && ra.rec && c->step >= 1) {
                 const double V = ra.V;
                 const double qs = -1.0 / (256.0 * M_PI * M_PI);
                 const double qr = qs * o[4], qi = qs * o[5];
@@ -2013,10 +2089,11 @@ hipError_t launch_pack(const Launch& L, int prec, const void* field, double* aos
     return hipGetLastError();
 }
 
-hipError_t launch_clover(const Launch& L, int prec, int only_theta)
+hipError_t launch_clover(const Launch& L, int prec, int only_theta, bool record)
 {
-    if (prec) CLGC_LAUNCH((k_clover<float, FAST_>), KIND_PLANE, only_theta);
-    else CLGC_LAUNCH((k_clover<double, FAST_>), KIND_PLANE, only_theta);
+    const int rec = record ? 1 : 0;
+    if (prec) CLGC_LAUNCH((k_clover<float, FAST_>), KIND_PLANE, only_theta, rec);
+    else CLGC_LAUNCH((k_clover<double, FAST_>), KIND_PLANE, only_theta, rec);
     return hipGetLastError();
 }
 
@@ -2029,6 +2106,12 @@ hipError_t launch_drift(const Launch& L, int prec, bool theta)
         if (theta) CLGC_LAUNCH((k_drift<double, true, FAST_>), KIND_DRIFT);
         else CLGC_LAUNCH((k_drift<double, false, FAST_>), KIND_DRIFT);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_record_charge(const Launch& L)
+{
+    CLGC_LAUNCH((k_record_charge<FAST_>), KIND_SITE);
     return hipGetLastError();
 }
 

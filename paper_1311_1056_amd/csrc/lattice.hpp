@@ -42,7 +42,7 @@ enum Kind : int {
 
 // what a finalize launch reduces
 enum Finalize : int { FIN_INIT = 0, FIN_UNORM = 1, FIN_DRIFT = 2, FIN_UPDATE = 3, FIN_COOL = 4,
-                      FIN_MEASURE = 6, FIN_RECORD = 7 };
+                      FIN_MEASURE = 6, FIN_RECORD = 7, FIN_RECORD_STEP = 8 };
 
 enum Status : int { ST_OK = 0, ST_NONFINITE = 1 };
 

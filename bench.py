@@ -486,6 +486,55 @@ def large_lattice(args):
     return out
 
 
+def mixed_vs_fp64(args, n_steps=300):
+    """Mixed precision against FP64 over whole trajectories at 24^4 and 32^4
+    (theta 1, seed 4, adaptive eps0 = 1e-2, 10 D_1 cooling steps per update):
+    both start from the same FP32-representable links and draw the same
+    Philox noise; each records P, Q and d at every step on the device.  The
+    first step's error is the per-step accuracy of the mixed path (gated at
+    1e-6 in the tests); later steps show how the CL dynamics amplify it."""
+    import numpy as np
+    import torch
+    import paper_1311_1056_amd as cl
+    kw = (1e-2, True, 10, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    out = {"steps": n_steps, "theta": 1.0, "seed": 4,
+           "err": "|mixed - FP64| / max(1, |FP64|) of the recorded observable at that step"}
+    for L in (24, 32):
+        dims = (L, L, L, L)
+        mx = cl.Lattice(dims, 6.0, 1.0, cl.CL_MIXED, seed=4)
+        mx.init(True, 0.3, 0.05)
+        fp = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=4)
+        fp.set_links(mx.get_links())
+        recs, ms = [], {}
+        for name, lat in (("mixed", mx), ("fp64", fp)):
+            lat.record_enable(True)
+            lat.run_prepare(*kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat.run_steps(n_steps, *kw)
+            torch.cuda.synchronize()
+            ms[name] = round(1e3 * (time.perf_counter() - t0) / n_steps, 4)
+            recs.append(lat.record_read(1, n_steps))
+            lat.close()
+        a, b = recs
+        cols = {"plaq": (3, 4), "q": (5, 6), "d": (2, None)}
+
+        def err(i, c):
+            re, im = cols[c]
+            va = a[i, re] + (1j * a[i, im] if im else 0)
+            vb = b[i, re] + (1j * b[i, im] if im else 0)
+            return float(abs(va - vb) / max(1.0, abs(vb)))
+        at = {}
+        for k in (1, 10, 100, n_steps):
+            if k <= n_steps:
+                at[str(k)] = {c: float(f"{err(k - 1, c):.3e}") for c in cols}
+        first_over = {c: next((i + 1 for i in range(n_steps) if err(i, c) > 1e-6), None) for c in cols}
+        out[f"{L}x{L}x{L}x{L}"] = {"err_at_step": at, "first_step_over_1e-6": first_over, "ms_per_step_recorded": ms,
+                                   "final_fp64": {"plaq": float(b[-1, 3]), "q": [float(b[-1, 5]), float(b[-1, 6])],
+                                                  "d": float(b[-1, 2])}}
+    return out
+
+
 def theta_points(args):
     """The 16^4 workload at theta = 0, 0.5 and 2 (theta = 1 is the main line)."""
     out = {}
@@ -885,6 +934,8 @@ def main():
         progress("32^4 leg done")
         out["theta_points"] = theta_points(args)
         progress("theta points done")
+        out["mixed_vs_fp64"] = mixed_vs_fp64(args)
+        progress("mixed vs FP64 trajectories done")
         out["cooling_modes"] = cooling_modes(args)
         progress("cooling modes done")
         out["chain"] = chain_workload(args)

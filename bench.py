@@ -535,6 +535,45 @@ def mixed_vs_fp64(args, n_steps=300):
     return out
 
 
+def theta_series(args, n_steps=500):
+    """The 16^4 workload as a Langevin-time series: 500 CL steps at theta =
+    0.5, 1 and 2 (seed 3, adaptive eps, 10 D_1 cooling steps), P, Q, S and
+    d recorded on the device at every step and summarised here: the running
+    mean of Q (the paper's observable), P and d over the second half, the
+    step sizes, and the time per recorded step."""
+    import numpy as np
+    import torch
+    import paper_1311_1056_amd as cl
+    kw = (1e-2, True, args.ncool, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    out = {"steps": n_steps, "dims": "16x16x16x16", "seed": 3}
+    for th in (0.5, 1.0, 2.0):
+        lat = cl.Lattice((16, 16, 16, 16), args.beta, th, cl.CL_FP64, seed=3)
+        lat.init(True, 0.3, 0.05)
+        lat.record_enable(True)
+        lat.run_prepare(*kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.run_steps(n_steps, *kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n_steps
+        r = lat.record_read(1, n_steps)
+        lat.close()
+        half = r[n_steps // 2:]
+        q = r[:, 5] + 1j * r[:, 6]
+        run_q = np.cumsum(q) / np.arange(1, n_steps + 1)
+        out[f"theta_{th}"] = {
+            "ms_per_step": round(1e3 * dt, 4),
+            "running_mean_Q": {str(k): [round(float(run_q[k - 1].real), 4), round(float(run_q[k - 1].imag), 4)]
+                               for k in (50, 100, 250, n_steps)},
+            "plaq_second_half": [round(float(half[:, 3].mean()), 6), round(float(half[:, 3].std()), 6)],
+            "d_after_cooling_second_half": [float(f"{half[:, 2].mean():.4e}"), float(f"{half[:, 2].max():.4e}")],
+            "d_before_cooling_second_half": float(f"{half[:, 1].mean():.4e}"),
+            "eps_mean": float(f"{r[:, 9].mean():.4e}"),
+            "langevin_time": round(float(r[:, 9].sum()), 4),
+        }
+    return out
+
+
 def theta_points(args):
     """The 16^4 workload at theta = 0, 0.5 and 2 (theta = 1 is the main line)."""
     out = {}
@@ -936,6 +975,8 @@ def main():
         progress("theta points done")
         out["mixed_vs_fp64"] = mixed_vs_fp64(args)
         progress("mixed vs FP64 trajectories done")
+        out["theta_series"] = theta_series(args)
+        progress("theta series done")
         out["cooling_modes"] = cooling_modes(args)
         progress("cooling modes done")
         out["chain"] = chain_workload(args)

@@ -45,7 +45,7 @@ Layout layout_of(const cl_lattice_desc& d)
     const size_t V = (size_t)d.dims[0] * d.dims[1] * d.dims[2] * d.dims[3];
     const size_t rs = d.precision == CL_MIXED ? sizeof(float) : sizeof(double);
     int nb[NKIND];
-    blocks_per_kind((int)V, nb);
+    blocks_per_kind((int)V, d.precision == CL_MIXED ? 1 : 0, nb);
     int maxb = 0;
     for (int k = 0; k < NKIND; ++k) maxb = nb[k] > maxb ? nb[k] : maxb;
     Layout L;
@@ -387,7 +387,7 @@ cl_status cl_lattice_create(const cl_lattice_desc* desc, void* dev_buf, size_t b
     a.eps0 = 1e-2;
     a.eps_c = 1e-2;
     a.alpha = 1.0;
-    blocks_per_kind(lat->V, a.nblk);
+    blocks_per_kind(lat->V, lat->prec == CL_MIXED ? 1 : 0, a.nblk);
 
     BatchHdr hdr;
     std::memset(&hdr, 0, sizeof hdr);

@@ -53,12 +53,15 @@ hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st);
 hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st);
 hipError_t launch_zero(double* p, int n, hipStream_t st);
 
-// Cooling kernels use at most kMaxCoolBlocks logical blocks per run (512
-// blocks of 256 threads at two waves per SIMD already fill the 256 CUs); a
-// block loops over contiguous chunks of 256 lanes.  The partial sums of one
-// cooling step then stay few enough that the next step's blocks reduce them
-// themselves, with no finalize launch in between.
-constexpr int kMaxCoolBlocks = 512;
+// Cooling kernels use at most kMaxCoolBlocks logical blocks per run; a block
+// loops over contiguous chunks of 256 lanes.  The partial sums of one cooling
+// step then stay few enough that the next step's blocks reduce them
+// themselves, with no finalize launch in between.  cool_blocks picks the
+// count: FP64 up to 512 (512 blocks of 256 threads at two waves per SIMD
+// already fill the 256 CUs); mixed precision, whose prefetching kernels run
+// best at about four chunks per block on large lattices, a quarter of the
+// chunks between 512 and 2048.
+constexpr int kMaxCoolBlocks = 2048;
 __host__ __device__ inline int cool_chunks_total(int V) { return (2 * V + kBlock - 1) / kBlock; }
 
 // the chunks [c0, c1) of logical block lb when nch chunks of kBlock lanes are
@@ -70,12 +73,23 @@ __host__ __device__ inline void chunk_range(int nch, int nblk, int lb, int& c0, 
     c1 = (lb + 1) * per < nch ? (lb + 1) * per : nch;
 }
 
-// logical blocks a run of V sites needs per kind
-inline void blocks_per_kind(int V, int out[NKIND])
+__host__ __device__ inline int cool_blocks(int V, int prec)
+{
+    const int nch = cool_chunks_total(V);
+    int cap = 512;
+    if (prec) {
+        cap = nch / 4;
+        cap = cap < 512 ? 512 : (cap > kMaxCoolBlocks ? kMaxCoolBlocks : cap);
+    }
+    return nch < cap ? nch : cap;
+}
+
+// logical blocks a run of V sites in precision prec (0 FP64, 1 mixed) needs per kind
+inline void blocks_per_kind(int V, int prec, int out[NKIND])
 {
     out[KIND_LINK] = (4 * V + kBlock - 1) / kBlock;
     out[KIND_SITE] = (V + kBlock - 1) / kBlock;
-    out[KIND_COOL] = cool_chunks_total(V) < kMaxCoolBlocks ? cool_chunks_total(V) : kMaxCoolBlocks;
+    out[KIND_COOL] = cool_blocks(V, prec);
     const int Vh = V / 2;
     out[KIND_PLANE] = 12 * ((Vh + kBlock - 1) / kBlock);            // (region, plane, parity)
     out[KIND_DRIFT] = 8 * ((Vh + kBlock - 1) / kBlock);             // (region, mu, parity)

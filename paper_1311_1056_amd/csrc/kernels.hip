@@ -2127,7 +2127,7 @@ hipError_t launch_cool(const Launch& L, int prec, int phase, int iter)
     // a single lattice whose cooling blocks loop over several chunks takes the
     // prefetching kernels (a batch keeps the plain ones: its runs are mostly
     // small, and the prefetching ones hold more registers)
-    if (L.fast && cool_chunks_total(L.one.V) > kMaxCoolBlocks) {
+    if (L.fast && cool_chunks_total(L.one.V) > L.one.nblk[KIND_COOL]) {
         if (prec) {
             if (phase) CLGC_LAUNCH((k_cool_apply_pf<float, FAST_>), KIND_COOL, iter);
             else CLGC_LAUNCH((k_cool_omega_pf<float, FAST_>), KIND_COOL, iter);

@@ -35,7 +35,7 @@ static void report(bool ok, const char* what, const int* d)
     if (!ok) ++g_fail;
 }
 
-static RunArgs args_of(const int* d)
+static RunArgs args_of(const int* d, int prec = 0)
 {
     RunArgs a;
     std::memset(&a, 0, sizeof a);
@@ -43,13 +43,13 @@ static RunArgs args_of(const int* d)
     a.Lh0 = d[0] / 2;
     a.V = d[0] * d[1] * d[2] * d[3];
     a.Vh = a.V / 2;
-    blocks_per_kind(a.V, a.nblk);
+    blocks_per_kind(a.V, prec, a.nblk);
     return a;
 }
 
-static void check_cooling(const int* d)
+static void check_cooling(const int* d, int prec)
 {
-    const RunArgs a = args_of(d);
+    const RunArgs a = args_of(d, prec);
     const int nch = cool_chunks_total(a.V), nblk = a.nblk[KIND_COOL];
     bool ok = nblk >= 1 && nblk <= kMaxCoolBlocks;
     for (int p = 0; p < 2 && ok; ++p) {
@@ -90,7 +90,9 @@ static void check_cooling(const int* d)
         for (int c = 0; c < nch; ++c) ok = ok && chunk[c] == 1;
         for (size_t l = 0; l < cnt.size(); ++l) ok = ok && cnt[l] == 1;
     }
-    report(ok, "cooling lanes own every link once (both parities)", d);
+    report(ok, prec ? "cooling lanes own every link once (both parities, mixed-precision block count)"
+                    : "cooling lanes own every link once (both parities, FP64 block count)",
+           d);
     // the update: 4V lanes in chunks over the cooling blocks
     std::vector<unsigned char> cnt((size_t)4 * a.V, 0);
     const int nu = (4 * a.V + kBlock - 1) / kBlock;
@@ -209,7 +211,8 @@ int main()
         {8, 8, 8, 8},    {12, 4, 4, 4},   {4, 6, 4, 8},    {8, 8, 8, 16},   {16, 16, 16, 16}, {24, 24, 24, 8},
         {18, 18, 18, 22}, {24, 24, 24, 16}, {32, 32, 32, 16}, {32, 32, 32, 32}, {46, 46, 46, 46}};
     for (const auto& d : shapes) {
-        check_cooling(d);
+        check_cooling(d, 0);
+        check_cooling(d, 1);
         check_regions(d);
     }
     for (int total : {1, 7, 8, 9, 64, 100, 512, 1000, 4096, 12345}) check_slots(total);

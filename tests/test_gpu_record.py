@@ -90,6 +90,32 @@ def test_record_matches_oracle_series(cl, orc, case):
     lat.close()
 
 
+def test_record_after_a_measurement(cl, orc):
+    """FP64 with a theta term records inside the step (the clover kernel's
+    plaquette traces and link norms, a charge pass over its field): after a
+    cl_measure the clover field is already valid, and the recorded step must
+    still rebuild it with its record partials.  Two calls, a measurement
+    before each."""
+    dims, beta, theta, seed = (4, 2, 4, 6), 5.8, 1.3, 9
+    lat = cl.Lattice(dims, beta, theta, cl.CL_FP64, seed=seed)
+    lat.init(True, 0.3, 0.05)
+    W = lat.get_links()
+    lat.record_enable(True)
+    lat.measure()
+    lat.run_steps(3, 5e-3, True, 4, 5e-3, 1.0, cl.CL_ALPHA_UNORM)
+    lat.measure()
+    lat.run_steps(2, 5e-3, True, 4, 5e-3, 1.0, cl.CL_ALPHA_UNORM)
+    got = lat.record_read(1, 5)
+    ref = oracle_series(orc, dims, W, beta, theta, seed, 5, 5e-3, True, 4, 5e-3, 1.0, 1)
+    scale = np.maximum(np.abs(ref), 1.0)
+    scale[:, [1, 2, 9, 10, 11]] = np.abs(ref[:, [1, 2, 9, 10, 11]])
+    scale[:, [7, 8]] = np.maximum(np.abs(ref[:, [7, 8]]), float(np.prod(dims)))
+    worst = float(np.nanmax(np.abs(got - ref)[:, 1:] / scale[:, 1:]))
+    say(f"record after measurements: worst relative error {worst:.2e}")
+    assert worst < 1e-12
+    lat.close()
+
+
 def test_record_mixed_against_fp64(cl):
     """Mixed precision records in FP64 from its FP32 links: its series stays
     within the mixed tolerances of the FP64 series (same start, same noise)."""

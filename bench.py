@@ -122,7 +122,7 @@ def algorithmic_cost(kind, V, rs, theta):
 def floor_bytes(kind, V, rs):
     """The byte floor's share of one launch: every sweep over the lattice (the
     CL update, each cooling step) reads and writes each link once, with
-    neighbours reused on chip; the drift, the clover field, the Omega pairs and
+    neighbours reused on chip; the drift, the clover field, the staged Omega and
     the second read of a two-kernel cooling step are overhead above it.  The
     update and the cooling step's applying kernel carry the sweeps' bytes."""
     if kind in ("update", "cool_apply", "cool_step"):

@@ -5,7 +5,8 @@
 //   [ per precision group: BatchHdr | RunArgs[kMaxRuns] | GatherRec[kMaxRuns] ]
 //   [ run heap: one cl_lattice region per admitted run (first-fit allocator) ]
 // A batch step launches each kernel kind once per precision group over the
-// concatenated logical blocks of the group's runs.  The launches use a fixed
+// concatenated logical blocks of the group's runs (the two groups as parallel
+// branches of the captured graph).  The launches use a fixed
 // persistent grid and read the run table from device memory, so the captured
 // step graph stays valid while runs come and go; it is keyed only by the
 // launch sequence (largest cooling count, theta / D_2 present, groups present).
@@ -55,6 +56,10 @@ struct cl_server {
     size_t arena_bytes = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    // the second precision group's branch of a captured step, and the events
+    // that fork it from and join it to the first
+    hipStream_t cap_stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Heap heap;
     size_t heap_base = 0;
     std::chrono::steady_clock::time_point t0;
@@ -221,10 +226,26 @@ cl_status ensure_graph(cl_server* s)
     cl_status st = CL_OK;
     hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int g = 0; g < 2 && st == CL_OK; ++g)
+        // With both precision groups present their steps are independent (their
+        // runs, tables and gather records are disjoint): the FP64 group on the
+        // capture stream, the mixed group on a second stream forked from it and
+        // joined back, so the graph holds two parallel branches whose kernels
+        // can share the GPU.
+        const bool both = key[0] && key[4];
+        hipStream_t st1 = both ? s->cap_stream2 : s->cap_stream;
+        if (both) {
+            e = hipEventRecord(s->ev_fork, s->cap_stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->ev_fork, 0);
+        }
+        for (int g = 0; g < 2 && st == CL_OK && e == hipSuccess; ++g)
             if (key[4 * g]) st = enqueue_group_step(s, g, key[4 * g + 1], key[4 * g + 2] != 0, key[4 * g + 3] != 0,
-                                                     s->cap_stream);
-        e = hipStreamEndCapture(s->cap_stream, &gph);
+                                                     g == 0 ? s->cap_stream : st1);
+        if (both && st == CL_OK && e == hipSuccess) {
+            e = hipEventRecord(s->ev_join, s->cap_stream2);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream, s->ev_join, 0);
+        }
+        const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &gph);
+        if (e == hipSuccess) e = e2;
     }
     if (st != CL_OK) {
         if (gph) (void)hipGraphDestroy(gph);
@@ -295,6 +316,9 @@ cl_status cl_server_create(void* arena, size_t arena_bytes, void* hip_stream, cl
     s->heap_base = off;
     s->heap.reset(arena_bytes - off);
     HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream2, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     *out = s.release();
     return CL_OK;
 }
@@ -443,6 +467,9 @@ cl_status cl_server_destroy(cl_server* s)
         if (r->lat) (void)cl_lattice_destroy(r->lat);
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->cap_stream2) (void)hipStreamDestroy(s->cap_stream2);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     for (int g = 0; g < 2; ++g) {
         if (s->h_hdr[g]) (void)hipHostFree(s->h_hdr[g]);
         if (s->h_runs[g]) (void)hipHostFree(s->h_runs[g]);

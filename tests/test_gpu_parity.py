@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from tests import latutil as lu
+from tests.golden import fixture as gf
 
 pytestmark = pytest.mark.gpu
 
@@ -186,4 +187,26 @@ def test_config1_trajectory(cl, orc):
     err = relerr(lat.get_links(), W)
     say(f"config1: final link rel err {err:.3e}, worst plaquette diff {worst:.3e}")
     assert err < 1e-11
+    lat.close()
+
+
+def test_config1_against_stored_values(cl):
+    """The same 4^4 workload through the captured multi-step path
+    (cl_run_steps), against the values tests/golden/ stores for it (written
+    by the oracle), read from the device record of every step."""
+    g = gf.read()
+    lat = cl.Lattice(gf.DIMS, gf.BETA, gf.THETA, cl.CL_FP64, gf.SEED)
+    lat.init(True, gf.SIGMA_X, gf.SIGMA_Y)
+    lat.record_enable(True)
+    lat.run_steps(gf.N_STEPS, gf.EPS, False, gf.N_COOL, gf.EPS_C, gf.ALPHA, gf.MODE)
+    rec = lat.record_read(1, gf.N_STEPS)
+    # record columns 1-4: d before and after the cooling steps, plaquette re and im
+    worst = float(np.max(np.abs(rec[:, 1:5] - g["steps"][:, 1:5])))
+    Uc = lu.to_c(lat.get_links())
+    link_err = max(abs(Uc[s, mu, i, j] - z) for s, mu, i, j, z in g["links"])
+    norm_err = abs(np.sum(np.abs(Uc) ** 2) - g["norm2"]) / g["norm2"]
+    say(f"config1 stored: worst per-step diff {worst:.3e}, sampled link diff {link_err:.3e}, norm {norm_err:.3e}")
+    assert worst < 1e-12
+    assert link_err < 1e-11
+    assert norm_err < 1e-12
     lat.close()

@@ -122,6 +122,33 @@ def test_production_size_16x4_full_step(cl, orc):
 
 
 @pytest.mark.slow
+def test_production_size_16x4_full_step_mixed(cl, orc):
+    """The mixed-precision leg of the benchmark in its launch configuration
+    (16^4, beta 6, theta 1, adaptive eps, 10 D_1 cooling steps, the captured
+    step graph) against the FP64 oracle from the same FP32-rounded links:
+    links within 1e-5 relative, observables within 1e-6."""
+    dims = (16, 16, 16, 16)
+    lat = cl.Lattice(dims, 6.0, 1.0, cl.CL_MIXED, seed=3)
+    lat.init(True, 0.3, 0.05)
+    U0 = lat.get_links()
+    lat.run_steps(1, 1e-2, True, 10, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    got = lat.get_links()
+    o = lat.measure()
+    W = U0.copy()
+    obs, _ = orc.run(dims, W, 6.0, 1.0, 3, 1, 1e-2, True, 10, 1e-2, 1.0, 1)
+    err = relerr(got, W)
+    q = complex(obs[0, 4], obs[0, 5])
+    say(f"16^4 mixed full step: link rel err {err:.2e}, |dP| {abs(o['plaq'] - complex(obs[0, 2], obs[0, 3])):.2e}, "
+        f"|dQ| {abs(o['q'] - q):.2e} (|Q| {abs(q):.2f}), |dd| {abs(o['d'] - obs[0, 1]):.2e}")
+    assert err <= 1e-5
+    assert abs(o["plaq"] - complex(obs[0, 2], obs[0, 3])) <= 1e-6
+    assert abs(o["q"] - q) <= 1e-6 * max(1.0, abs(q))
+    assert abs(o["d"] - obs[0, 1]) <= 1e-6
+    assert abs(o["eps"] - obs[0, 6]) <= 1e-5 * obs[0, 6]
+    lat.close()
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("dims,precs", [((24, 24, 24, 24), (1, 0)), ((32, 32, 32, 32), (1,)),
                                         ((46, 46, 46, 46), (0,)), ((56, 56, 56, 56), (1,))])
 def test_large_lattice_sampled_drift(cl, orc, dims, precs):

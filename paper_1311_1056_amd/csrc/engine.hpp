@@ -53,10 +53,11 @@ hipError_t launch_write_args(RunArgs* dst, const RunArgs& src, hipStream_t st);
 hipError_t launch_write_state(Ctrl* c, int64_t step, double bound, hipStream_t st);
 hipError_t launch_zero(double* p, int n, hipStream_t st);
 
-// Cooling kernels use at most kMaxCoolBlocks logical blocks per run; a block
-// loops over contiguous chunks of 256 lanes.  The partial sums of one cooling
-// step then stay few enough that the next step's blocks reduce them
-// themselves, with no finalize launch in between.  cool_blocks picks the
+// The applying cooling kernel, the update and the gradient-norm pass use at
+// most kMaxCoolBlocks logical blocks per run; a block loops over contiguous
+// chunks of 256 lanes.  The partial sums of one cooling step then stay few
+// enough that the next step's blocks reduce them themselves, with no
+// finalize launch in between.  cool_blocks picks the
 // count: FP64 up to 512 (512 blocks of 256 threads at two waves per SIMD
 // already fill the 256 CUs); mixed precision, whose prefetching kernels run
 // best at about four chunks per block on large lattices, a quarter of the
@@ -84,6 +85,17 @@ __host__ __device__ inline int cool_blocks(int V, int prec)
     return nch < cap ? nch : cap;
 }
 
+// Logical blocks of the omega kernel.  It writes no partial sums (it reads
+// the applying kernel's and the update's, nblk[KIND_COOL] of them), so its
+// count is its own: FP64 one chunk per block, where the plain kernel (about
+// 100 registers, four waves per SIMD) beats the prefetching one on large
+// lattices; mixed precision the cooling count (its prefetching kernel, four
+// chunks per block on large lattices).
+__host__ __device__ inline int omega_blocks(int V, int prec)
+{
+    return prec ? cool_blocks(V, prec) : cool_chunks_total(V);
+}
+
 // logical blocks a run of V sites in precision prec (0 FP64, 1 mixed) needs per kind
 inline void blocks_per_kind(int V, int prec, int out[NKIND])
 {
@@ -93,6 +105,7 @@ inline void blocks_per_kind(int V, int prec, int out[NKIND])
     const int Vh = V / 2;
     out[KIND_PLANE] = 12 * ((Vh + kBlock - 1) / kBlock);            // (region, plane, parity)
     out[KIND_DRIFT] = 8 * ((Vh + kBlock - 1) / kBlock);             // (region, mu, parity)
+    out[KIND_OMEGA] = omega_blocks(V, prec);
 }
 
 constexpr int kNumPartials = 8;  // partial values per logical block of the widest kind

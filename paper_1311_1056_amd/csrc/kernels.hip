@@ -1220,12 +1220,12 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
 {
     __shared__ CoolShare<T> sh;
     int buf = 0;
-    CLGC_FOR_BLOCKS(KIND_COOL)
+    CLGC_FOR_BLOCKS(KIND_OMEGA)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
         int cb0, cb1;
-        chunk_range(nch, ra.nblk[KIND_COOL], lb, cb0, cb1);
+        chunk_range(nch, ra.nblk[KIND_OMEGA], lb, cb0, cb1);
         for (int c = cb0; c < cb1; ++c) {
             int h, mu;
             cool_lane(c, (int)threadIdx.x, h, mu);
@@ -1370,12 +1370,12 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
 {
     __shared__ CoolShare<T> sh;
     int buf = 0;
-    CLGC_FOR_BLOCKS(KIND_COOL)
+    CLGC_FOR_BLOCKS(KIND_OMEGA)
     Ctrl* cr = ra.ctrl;
     if (iter < ra.n_cool) {
         const int nch = cool_chunks_total(ra.V);
         int c0, c1;
-        chunk_range(nch, ra.nblk[KIND_COOL], lb, c0, c1);
+        chunk_range(nch, ra.nblk[KIND_OMEGA], lb, c0, c1);
         const int mu = (int)threadIdx.x / kCoolSites;
         int h = 0;
         bool lok = false;
@@ -2124,25 +2124,26 @@ hipError_t launch_update(const Launch& L, int prec)
 
 hipError_t launch_cool(const Launch& L, int prec, int phase, int iter)
 {
-    // a single lattice whose cooling blocks loop over several chunks takes the
-    // prefetching kernels (a batch keeps the plain ones: its runs are mostly
+    // a single lattice whose blocks loop over several chunks takes the
+    // prefetching kernel (a batch keeps the plain ones: its runs are mostly
     // small, and the prefetching ones hold more registers)
-    if (L.fast && cool_chunks_total(L.one.V) > L.one.nblk[KIND_COOL]) {
+    const int kind = phase ? KIND_COOL : KIND_OMEGA;
+    if (L.fast && cool_chunks_total(L.one.V) > L.one.nblk[kind]) {
         if (prec) {
             if (phase) CLGC_LAUNCH((k_cool_apply_pf<float, FAST_>), KIND_COOL, iter);
-            else CLGC_LAUNCH((k_cool_omega_pf<float, FAST_>), KIND_COOL, iter);
+            else CLGC_LAUNCH((k_cool_omega_pf<float, FAST_>), KIND_OMEGA, iter);
         } else {
             if (phase) CLGC_LAUNCH((k_cool_apply_pf<double, FAST_>), KIND_COOL, iter);
-            else CLGC_LAUNCH((k_cool_omega_pf<double, FAST_>), KIND_COOL, iter);
+            else CLGC_LAUNCH((k_cool_omega_pf<double, FAST_>), KIND_OMEGA, iter);
         }
         return hipGetLastError();
     }
     if (prec) {
         if (phase) CLGC_LAUNCH((k_cool_apply<float, FAST_>), KIND_COOL, iter);
-        else CLGC_LAUNCH((k_cool_omega<float, FAST_>), KIND_COOL, iter);
+        else CLGC_LAUNCH((k_cool_omega<float, FAST_>), KIND_OMEGA, iter);
     } else {
         if (phase) CLGC_LAUNCH((k_cool_apply<double, FAST_>), KIND_COOL, iter);
-        else CLGC_LAUNCH((k_cool_omega<double, FAST_>), KIND_COOL, iter);
+        else CLGC_LAUNCH((k_cool_omega<double, FAST_>), KIND_OMEGA, iter);
     }
     return hipGetLastError();
 }

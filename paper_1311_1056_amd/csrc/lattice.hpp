@@ -37,7 +37,8 @@ enum Kind : int {
     KIND_COOL = 2,   // one (site of one parity, mu): cooling  (2V threads)
     KIND_PLANE = 3,  // one (site, plane): clover field        (6V threads)
     KIND_DRIFT = 4,  // one (link, 256-site region): drift    (4V threads)
-    NKIND = 5
+    KIND_OMEGA = 5,  // one (site of one parity, mu): the omega kernel of a cooling step (2V threads)
+    NKIND = 6
 };
 
 // what a finalize launch reduces

@@ -93,6 +93,21 @@ static void check_cooling(const int* d, int prec)
     report(ok, prec ? "cooling lanes own every link once (both parities, mixed-precision block count)"
                     : "cooling lanes own every link once (both parities, FP64 block count)",
            d);
+    // the omega kernel deals the same chunks over its own block count
+    {
+        const int nom = a.nblk[KIND_OMEGA];
+        bool ook = nom >= 1 && nom <= nch;
+        std::vector<unsigned char> chunk(nch, 0);
+        for (int lb = 0; lb < nom && ook; ++lb) {
+            int c0, c1;
+            chunk_range(nch, nom, lb, c0, c1);
+            for (int c = c0; c < c1; ++c) chunk[c]++;
+        }
+        for (int c = 0; c < nch; ++c) ook = ook && chunk[c] == 1;
+        report(ook, prec ? "omega blocks cover every chunk once (mixed-precision block count)"
+                         : "omega blocks cover every chunk once (FP64 block count)",
+               d);
+    }
     // the update: 4V lanes in chunks over the cooling blocks
     std::vector<unsigned char> cnt((size_t)4 * a.V, 0);
     const int nu = (4 * a.V + kBlock - 1) / kBlock;

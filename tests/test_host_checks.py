@@ -45,6 +45,7 @@ def test_device_index_arithmetic_on_host():
                                "-I", os.path.join(ROOT, "include"), src, "-o", exe])
     out = _run(exe)
     assert out.count("ok cooling lanes own every link once") >= 10
+    assert out.count("ok omega blocks cover every chunk once") >= 10
 
 
 def test_server_admission_and_allocator_on_a_fake_clock():

@@ -665,9 +665,9 @@ __device__ __forceinline__ cx<double> det_renorm_factor(cx<double> d)
 // per-XCD maxima its blocks left in the control block), so no finalize runs
 // between the two kernels; block 0 records eps, K_max and the bound and
 // clears the slots the next step's drift will use.  The update runs on the
-// cooling kernels' logical blocks (at most kMaxCoolBlocks, each looping over
-// chunks of 256 links) and leaves its unitarity-norm partials where the next
-// cooling step's wavefronts sum them.
+// applying cooling kernel's logical blocks (KIND_COOL: at most
+// kMaxCoolBlocks, each looping over chunks of 256 links) and leaves its
+// unitarity-norm partials where the next omega kernel's wavefronts sum them.
 template <typename T, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_update(const KArgs ka)
 {
@@ -1238,41 +1238,46 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega(const KArgs ka, int iter)
                 h_add_uudag(G, load_mat(Uc, of, 4 * ra.V));
                 h_sub_udagu(G, load_mat(Uc, ob, 4 * ra.V));
             }
-            // Each wavefront reads the status for itself (there is no barrier
-            // here).  Within this launch the word changes only below, in block
-            // 0, when the norm that every wavefront computes identically is not
-            // finite: then every Omega is non-finite and nothing reads them.
-            const bool ok = cr->status == ST_OK;
-            // unitarity norm entering the step: the partials of the CL update just
-            // applied or of the previous cooling step; else (a cooling call on its
-            // own) the finalized norm
-            const bool pend = iter == 0 && cr->upd_pending;
-            const double un = iter == 0 && !pend ? cr->unorm : wave_cool_sum(ra);
-            // D_2 = mean |f_ax| from the gradient-norm pass just before (its
-            // partials, one per cooling logical block)
-            const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
-            const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
-                                                 : (ra.mode == 2 ? ra.alpha / d2 : ra.alpha);
-            if (ok && lb == 0 && c == 0 && threadIdx.x == 0) {
-                cr->alpha_cur = alpha_ad;
-                cr->unorm = un;
-                if (pend) {
-                    // the update's finalization: its norm, and the step is taken
-                    cr->d_pre = un / (12.0 * ra.V) - 1.0;
-                    cr->step = cr->step + 1;
-                }
-                if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
-                if (iter < kMaxCoolHist) {
-                    cr->hist_alpha[iter] = alpha_ad;
-                    cr->hist_un[iter] = un;
-                    cr->hist_n = iter + 1;
+            // wavefront 0 forms Omega, wavefront 1 Omega^-1 where it is staged;
+            // the others only contribute their shares of G and need no run state
+            const bool expw = mu < (kStageInverse<T> ? 2 : 1);
+            bool ok = false;
+            double alpha_ad = 0.0;
+            if (expw) {
+                // Each of these wavefronts reads the status for itself (there is
+                // no barrier here).  Within this launch the word changes only
+                // below, in block 0, when the norm that every one of them
+                // computes identically is not finite: then every Omega is
+                // non-finite and nothing reads them.
+                ok = cr->status == ST_OK;
+                // unitarity norm entering the step: the partials of the CL update
+                // just applied or of the previous cooling step; else (a cooling
+                // call on its own) the finalized norm
+                const bool pend = iter == 0 && cr->upd_pending;
+                const double un = iter == 0 && !pend ? cr->unorm : wave_cool_sum(ra);
+                // D_2 = mean |f_ax| from the gradient-norm pass just before (its
+                // partials, one per logical block of the applying kernel)
+                const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
+                alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V)) : (ra.mode == 2 ? ra.alpha / d2 : ra.alpha);
+                if (ok && lb == 0 && c == 0 && threadIdx.x == 0) {
+                    cr->alpha_cur = alpha_ad;
+                    cr->unorm = un;
+                    if (pend) {
+                        // the update's finalization: its norm, and the step is taken
+                        cr->d_pre = un / (12.0 * ra.V) - 1.0;
+                        cr->step = cr->step + 1;
+                    }
+                    if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
+                    if (iter < kMaxCoolHist) {
+                        cr->hist_alpha[iter] = alpha_ad;
+                        cr->hist_un[iter] = un;
+                        cr->hist_n = iter + 1;
+                    }
                 }
             }
-            // wavefront 0 forms Omega, wavefront 1 Omega^-1 where it is staged
-            // (the others only contribute their shares)
-            const T coef = T(-4.0 * ra.eps_c * alpha_ad);
             const herm3<T> Gx = site_sum(G, sh, buf);
-            if (mu < (kStageInverse<T> ? 2 : 1)) {
+            if (expw) {
+                const T coef = T(-4.0 * ra.eps_c * alpha_ad);
                 herm3<T> E;
                 site_omega_one(Gx, mu == 1 ? -coef : coef, E);
                 if (ok && lane_ok) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
@@ -1342,12 +1347,13 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply(const KArgs ka, int iter)
     CLGC_END_BLOCKS
 }
 
-// The same cooling step for a lattice whose blocks loop over several chunks
-// (more than kMaxCoolBlocks chunks): each wavefront issues the next chunk's
-// loads before it works on the current one, so HBM keeps streaming while the
-// chunk's arithmetic runs.  The run state is read once per wavefront.  Same
-// products in the same order as k_cool_omega / k_cool_apply: the results are
-// bitwise equal.
+// The same cooling step for a single lattice whose blocks loop over several
+// chunks (more chunks than the kernel's logical blocks: the applying kernel
+// above 16^4 sites, and in mixed precision the omega kernel): each wavefront
+// issues the next chunk's loads before it works on the current one, so HBM
+// keeps streaming while the chunk's arithmetic runs.  The run state is read
+// once per wavefront.  Same products in the same order as k_cool_omega /
+// k_cool_apply: the results are bitwise equal.
 
 // lane (h, mu) of chunk c: U_mu(x) and U_mu(x - mu) of even site h
 template <typename T>
@@ -1381,25 +1387,30 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
         bool lok = false;
         mat3<T> Af, Ab;
         if (c0 < c1) omega_loads(ra, c0, h, lok, Af, Ab);
-        // the run state, as in k_cool_omega
-        const bool ok = cr->status == ST_OK;
-        const bool pend = iter == 0 && cr->upd_pending;
-        const double un = iter == 0 && !pend ? cr->unorm : wave_cool_sum(ra);
-        const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
-        const double alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V))
-                                             : (ra.mode == 2 ? ra.alpha / d2 : ra.alpha);
-        if (ok && lb == 0 && c0 < c1 && threadIdx.x == 0) {
-            cr->alpha_cur = alpha_ad;
-            cr->unorm = un;
-            if (pend) {
-                cr->d_pre = un / (12.0 * ra.V) - 1.0;
-                cr->step = cr->step + 1;
-            }
-            if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
-            if (iter < kMaxCoolHist) {
-                cr->hist_alpha[iter] = alpha_ad;
-                cr->hist_un[iter] = un;
-                cr->hist_n = iter + 1;
+        // the run state, as in k_cool_omega: read by the wavefronts that form
+        // an exponential only
+        const bool expw = mu < (kStageInverse<T> ? 2 : 1);
+        bool ok = false;
+        double alpha_ad = 0.0;
+        if (expw) {
+            ok = cr->status == ST_OK;
+            const bool pend = iter == 0 && cr->upd_pending;
+            const double un = iter == 0 && !pend ? cr->unorm : wave_cool_sum(ra);
+            const double d2 = ra.mode == 2 ? wave_sum_of(ra.part, ra.nblk[KIND_COOL]) / (8.0 * ra.V) : 1.0;
+            alpha_ad = ra.mode == 1 ? ra.alpha / (un / (4.0 * ra.V)) : (ra.mode == 2 ? ra.alpha / d2 : ra.alpha);
+            if (ok && lb == 0 && c0 < c1 && threadIdx.x == 0) {
+                cr->alpha_cur = alpha_ad;
+                cr->unorm = un;
+                if (pend) {
+                    cr->d_pre = un / (12.0 * ra.V) - 1.0;
+                    cr->step = cr->step + 1;
+                }
+                if (!isfinite(un) || !(d2 > 0.0) || !isfinite(alpha_ad)) cr->status = ST_NONFINITE;
+                if (iter < kMaxCoolHist) {
+                    cr->hist_alpha[iter] = alpha_ad;
+                    cr->hist_un[iter] = un;
+                    cr->hist_n = iter + 1;
+                }
             }
         }
         const T coef = T(-4.0 * ra.eps_c * alpha_ad);
@@ -1414,7 +1425,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_omega_pf(const KArgs ka, int it
                 h_sub_udagu(G, Ab);
             }
             const herm3<T> Gx = site_sum(G, sh, buf);
-            if (mu < (kStageInverse<T> ? 2 : 1)) {
+            if (expw) {
                 herm3<T> E;
                 site_omega_one(Gx, mu == 1 ? -coef : coef, E);
                 if (ok && lok) store_herm(omega_rsrc<T>(ra), h, ra.Vh, mu == 0 ? 0 : 9, E);
@@ -1510,7 +1521,7 @@ __global__ void __launch_bounds__(kBlock) k_cool_apply_pf(const KArgs ka, int it
 
 // D_2 = mean over (a, x) of |f_ax| on the configuration entering a cooling
 // step, f_ax = 2 Tr(lambda_a G_x).  Two lanes per site (directions 0, 1 and
-// 2, 3, joined by one shuffle), on the cooling kernels' logical blocks: the
+// 2, 3, joined by one shuffle), on the applying kernel's logical blocks: the
 // chunks of kBlock lanes are then exactly as many as the cooling chunks, so
 // every block (and every XCD) has work, and the next omega kernel's
 // wavefronts sum the <= kMaxCoolBlocks partials themselves.

@@ -221,6 +221,41 @@ def test_large_lattice_mixed_against_fp64_step(cl, dims):
     fp.close()
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(24, 24, 24, 24), (32, 32, 32, 32)])
+def test_large_lattice_full_step_against_oracle(cl, orc, dims):
+    """The mixed-precision workload's sizes, 24^4 and 32^4 (theta 1, seed 4,
+    adaptive eps, 10 D_1 cooling steps), one whole step in the captured launch
+    configuration against the oracle stepping the same links: the FP64 path
+    at 1e-12, the mixed path at its stated bounds (links 1e-5 relative; P, Q
+    and d within 1e-6 of max(1, |value|))."""
+    mx = cl.Lattice(dims, 6.0, 1.0, cl.CL_MIXED, seed=4)
+    mx.init(True, 0.3, 0.05)
+    W = mx.get_links()  # FP32-representable: every side starts from these
+    fp = cl.Lattice(dims, 6.0, 1.0, cl.CL_FP64, seed=4)
+    fp.set_links(W)
+    for lat in (mx, fp):
+        lat.run_steps(1, 1e-2, True, 10, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    a, b = mx.measure(), fp.measure()
+    obs, _ = orc.run(dims, W, 6.0, 1.0, 4, 1, 1e-2, True, 10, 1e-2, 1.0, 1)
+    ref = {"plaq": complex(obs[0, 2], obs[0, 3]), "q": complex(obs[0, 4], obs[0, 5]), "d": obs[0, 1],
+           "eps": obs[0, 6]}
+    ef = relerr(fp.get_links(), W)
+    em = relerr(mx.get_links(), W)
+    say(f"{dims}: FP64 link rel err {ef:.2e}, mixed {em:.2e}; |Q| {abs(ref['q']):.2f}")
+    assert ef < 1e-12
+    assert em <= 1e-5
+    assert abs(b["eps"] - ref["eps"]) <= 1e-13 * ref["eps"]
+    assert abs(a["eps"] - ref["eps"]) <= 1e-5 * ref["eps"]
+    for k in ("plaq", "q", "d"):
+        scale = max(1.0, abs(ref[k]))
+        say(f"  {k}: FP64 {abs(b[k] - ref[k]) / scale:.2e}, mixed {abs(a[k] - ref[k]) / scale:.2e}")
+        assert abs(b[k] - ref[k]) <= 1e-11 * scale, k
+        assert abs(a[k] - ref[k]) <= 1e-6 * scale, k
+    mx.close()
+    fp.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_minimum_and_ragged_lattices(cl, orc, prec):
     """2^4 (every neighbour wraps) and extents with a ragged last block (a

@@ -275,6 +275,45 @@ def test_minimum_and_ragged_lattices(cl, orc, prec):
         lat.close()
 
 
+def test_zero_step_and_zero_cooling_calls(cl, orc):
+    """Degenerate calls: zero CL steps and zero cooling steps change nothing;
+    CL steps without cooling, replayed from the captured graphs (a block of
+    eight steps and one more: the norm is then finalized every step, and with
+    the theta term in FP64 the record is taken inside the step), follow the
+    oracle at 1e-12."""
+    dims, beta, theta, seed = (4, 4, 4, 6), 5.9, 0.7, 6
+    lat = cl.Lattice(dims, beta, theta, cl.CL_FP64, seed)
+    lat.init(True, 0.3, 0.05)
+    U0 = lat.get_links()
+    o0 = lat.measure()
+    lat.run_steps(0, 1e-2, True, 5, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    d = lat.gauge_cool(0, 1e-2, 1.0, cl.CL_ALPHA_UNORM)
+    assert np.array_equal(lat.get_links(), U0)
+    o1 = lat.measure()
+    assert o1["step"] == o0["step"] == 0
+    assert o1["plaq"] == o0["plaq"] and o1["q"] == o0["q"]
+    assert abs(d - o0["d"]) <= 1e-12 * o0["d"]
+    lat.record_enable(True)
+    lat.run_steps(9, 1e-2, True, 0, 1e-2, 1.0, cl.CL_ALPHA_FIXED)
+    rec = lat.record_read(1, 9)
+    W = U0.copy()
+    obs, _ = orc.run(dims, W, beta, theta, seed, 9, 1e-2, True, 0, 1e-2, 1.0, 0)
+    err = relerr(lat.get_links(), W)
+    say(f"9 CL steps without cooling: link rel err {err:.2e}")
+    assert err < 1e-12
+    assert np.array_equal(rec[:, 0], np.arange(1, 10))
+    # record columns against the oracle's: d before and after the (empty)
+    # cooling, P re/im, Q re/im, eps, K_max
+    for rc, oc in ((1, 0), (2, 1), (3, 2), (4, 3), (5, 4), (6, 5), (9, 6), (10, 7)):
+        ref = obs[:, oc]
+        scale = np.abs(ref) if rc in (1, 2, 9, 10) else np.maximum(np.abs(ref), 1.0)
+        assert np.all(np.abs(rec[:, rc] - ref) <= 1e-12 * scale), (rc, rec[:, rc], ref)
+    # without cooling d before and after it are one value, formed here by two
+    # different reductions (the update's norm partials, the record's own sum)
+    assert np.all(np.abs(rec[:, 1] - rec[:, 2]) <= 1e-13 * rec[:, 2])
+    lat.close()
+
+
 def test_errors(cl):
     with pytest.raises(cl.ClError) as e:
         cl.Lattice((3, 4, 4, 4), 6.0)

@@ -79,6 +79,11 @@ def test_admission_by_budget(cl):
     desc = cl.make_desc((8, 8, 8, 8), 6.0)
     per_run = cl.cl_lattice_bytes(desc)
     srv = cl.Server(2 * per_run + (4 << 20))  # tables + two 8^4 runs
+    # an empty server steps nothing and retires nothing; a run of no steps is refused
+    assert srv.step(4) == (0, 0) and srv.poll() == []
+    with pytest.raises(cl.ClError) as e:
+        srv.submit((8, 8, 8, 8), 6.0, 0.5, 0, 1, n_steps=0)
+    assert e.value.status == cl.CL_EINVAL
     for i in range(5):
         srv.submit((8, 8, 8, 8), 6.0, 0.5, 0, 200 + i, n_steps=2, n_cool=2, tag=i)
     a, p = srv.step()

@@ -479,12 +479,12 @@ __device__ __forceinline__ void theta_loop_lds(const RunArgs& ra, const cx<T>* _
     const mat3<T> Pm = R * e3;
     Q = m_scale(Q, cts);
     const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
-    mat3<T> a = m_scale(Pm, cb);
+    mat3<T> a = m_scale_i(Pm, cb.im);
     m_mac(a, Q, Pm);
     m_mac(a, Pm, X0s);
     lds_acc_add(accA, a);
     const mat3<T> Pa = m_adj(Pm);
-    mat3<T> b = m_scale(Pa, mcb);
+    mat3<T> b = m_scale_i(Pa, mcb.im);
     m_mac(b, Pa, Q);
     m_mac(b, X0s, Pa);
     lds_acc_add(accB, b);
@@ -501,6 +501,13 @@ __global__ void __launch_bounds__(kBlock, 2) k_drift(const KArgs ka)
 {
     __shared__ double lds[8];
     constexpr bool kAccLds = sizeof(T) == 8 && THETA;
+    // FP64 forms e^-1 = adj(e) / det e, exact for any links.  FP32 links are
+    // in SL(3,C) to their rounding (|det - 1| ~ 1e-7, renormalised in FP64
+    // at every update), so the FP32 walk takes adj(e) itself: that changes
+    // its drift by as much, far inside the mixed path's tolerance, and saves
+    // the two reciprocals and scalings of every loop (the FP32 drift is
+    // bound by instruction issue)
+    constexpr bool kExactInverse = sizeof(T) == 8;
     __shared__ T accl[kAccLds ? 36 * kBlock : 1];
     CLGC_FOR_BLOCKS(KIND_DRIFT)
     // logical block -> (region of 256 half-indices, direction, parity): the eight
@@ -566,8 +573,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_drift(const KArgs ka)
                     mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
                     if (s > 0) e3 = m_adj(e3);
                     Pm = Pm * e3;
-                    m_axpy(A, cb, Pm);
-                    m_axpy(B, mcb, m_adj(Pm));
+                    m_axpy_i(A, cb.im, Pm);
+                    m_axpy_i(B, mcb.im, m_adj(Pm));
                 } else {
                     const T sig = T(s * (nu > mu ? 1 : -1) * dual_sign(Pl));
                     const cx<T> cts = {sig * ct.re, sig * ct.im};
@@ -575,15 +582,16 @@ __global__ void __launch_bounds__(kBlock, 2) k_drift(const KArgs ka)
                     // Y = X2 + e2 X3 e2^-1.  Inverses from the raw links: e2 =
                     // adj(ub) has e2^-1 = ub / det ub, and e1^-1 is adj(ua) / det ua
                     // (s > 0) or ua / det ua (s < 0, e1 = adj(ua)); exact for any
-                    // links, not only det U = 1.
+                    // links, not only det U = 1 (the determinants only in FP64,
+                    // kExactInverse).
                     const mat3<T> ub = load_mat(Ub, link_off(ra, mu, d3), us);
                     const mat3<T> X3 = load_mat(Fb, fo + link_off(ra, 0, d3), fs);
                     const mat3<T> e2 = m_adj(ub);
                     mat3<T> Y = (e2 * X3) * ub;
-                    Y = m_scale(Y, inv_det(ub, e2)) + load_mat(Fb, fo + link_off(ra, 0, d2), fs);
+                    if constexpr (kExactInverse) Y = m_scale(Y, inv_det(ub, e2));
+                    Y = Y + load_mat(Fb, fo + link_off(ra, 0, d2), fs);
                     const mat3<T> ua = load_mat(Ub, oa, us);
                     const mat3<T> ua_adj = m_adj(ua);
-                    const cx<T> ida = inv_det(ua, ua_adj);
                     mat3<T> e1, e1i;
                     if (s > 0) {
                         e1 = ua;
@@ -593,13 +601,15 @@ __global__ void __launch_bounds__(kBlock, 2) k_drift(const KArgs ka)
                         e1i = ua;
                     }
                     const mat3<T> R = e1 * e2;
-                    mat3<T> Q = m_scale((e1 * Y) * e1i, ida) + load_mat(Fb, fo + link_off(ra, 0, d1), fs);
+                    mat3<T> Q = (e1 * Y) * e1i;
+                    if constexpr (kExactInverse) Q = m_scale(Q, inv_det(ua, ua_adj));
+                    Q = Q + load_mat(Fb, fo + link_off(ra, 0, d1), fs);
                     mat3<T> e3 = load_mat(Ub, link_off(ra, nu, s > 0 ? x : d3), us);
                     if (s > 0) e3 = m_adj(e3);
                     const mat3<T> Pm = R * e3;
                     const mat3<T> Pa = m_adj(Pm);
-                    m_axpy(A, cb, Pm);
-                    m_axpy(B, mcb, Pa);
+                    m_axpy_i(A, cb.im, Pm);
+                    m_axpy_i(B, mcb.im, Pa);
                     Q = m_scale(Q, cts);
                     m_mac(A, Q, Pm);
                     m_mac(B, Pa, Q);

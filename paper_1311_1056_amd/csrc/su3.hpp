@@ -139,6 +139,29 @@ __device__ __forceinline__ mat3<R> m_scale(const mat3<R>& a, cx<R> c)
     return r;
 }
 
+// a times the purely imaginary scalar i c (c real): two products per entry
+template <typename R>
+__device__ __forceinline__ mat3<R> m_scale_i(const mat3<R>& a, R c)
+{
+    mat3<R> r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r.e[i][j] = {-c * a.e[i][j].im, c * a.e[i][j].re};
+    return r;
+}
+
+// acc += i c m (c real): two fused multiply-adds per entry
+template <typename R>
+__device__ __forceinline__ void m_axpy_i(mat3<R>& acc, R c, const mat3<R>& m)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            acc.e[i][j] = {fma(-c, m.e[i][j].im, acc.e[i][j].re), fma(c, m.e[i][j].re, acc.e[i][j].im)};
+}
+
 template <typename R>
 __device__ __forceinline__ cx<R> m_tr(const mat3<R>& a) { return a.e[0][0] + a.e[1][1] + a.e[2][2]; }
 

@@ -610,10 +610,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_drift(const KArgs ka)
                     const mat3<T> Pa = m_adj(Pm);
                     m_axpy_i(A, cb.im, Pm);
                     m_axpy_i(B, mcb.im, Pa);
-                    Q = m_scale(Q, cts);
+                    Q = m_scale_z(Q, cts);
                     m_mac(A, Q, Pm);
                     m_mac(B, Pa, Q);
-                    const mat3<T> X0s = m_scale(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
+                    const mat3<T> X0s = m_scale_z(load_mat(Fb, fo + p * ra.Vh + h, fs), cts);
                     m_mac(A, Pm, X0s);
                     m_mac(B, X0s, Pa);
                 }

@@ -151,6 +151,24 @@ __device__ __forceinline__ mat3<R> m_scale_i(const mat3<R>& a, R c)
     return r;
 }
 
+// a c for a complex c that is often real (a real theta): two products per
+// entry when Im c = 0, the full complex product otherwise (c uniform across
+// the wavefront, so the branch does not diverge)
+template <typename R>
+__device__ __forceinline__ mat3<R> m_scale_z(const mat3<R>& a, cx<R> c)
+{
+    mat3<R> r;
+    if (c.im == R(0)) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) r.e[i][j] = {c.re * a.e[i][j].re, c.re * a.e[i][j].im};
+    } else {
+        r = m_scale(a, c);
+    }
+    return r;
+}
+
 // acc += i c m (c real): two fused multiply-adds per entry
 template <typename R>
 __device__ __forceinline__ void m_axpy_i(mat3<R>& acc, R c, const mat3<R>& m)

@@ -86,15 +86,20 @@ def test_mixed_precision_step_tolerance(cl, orc, theta):
     lat.close()
 
 
-def test_mixed_drift_tolerance(cl, orc):
+@pytest.mark.parametrize("theta", [1.0, 0.6 - 0.8j])
+def test_mixed_drift_tolerance(cl, orc, theta):
+    """The FP32 drift (real and complex theta: the walk scales the charge
+    insertions by a real factor in the first case) against the oracle."""
     dims = (4, 4, 4, 4)
     rng = np.random.default_rng(7)
     U = lu.random_links(rng, dims, 0.5, 0.2)
-    lat = cl.Lattice(dims, 6.0, 1.0, cl.CL_MIXED)
+    lat = cl.Lattice(dims, 6.0, theta, cl.CL_MIXED)
     lat.set_links(U)
     Ur = lat.get_links()
     K = lat.compute_drift()
-    assert relerr(K, orc.drift(dims, Ur, 6.0, 1.0)) < 1e-5
+    err = relerr(K, orc.drift(dims, Ur, 6.0, theta))
+    say(f"mixed drift theta={theta}: rel err {err:.2e}")
+    assert err < 1e-5
     lat.close()
 
 
